@@ -1,0 +1,128 @@
+"""FCT1, the Fast Cauchy Transform Pi1 = 4 B C H~ (test infrastructure only).
+
+Section "FCT1 Construction: via a Low-coherence Matrix" defines
+
+* H~ in R^{2n x n}: block diagonal with n/s blocks G_s = [H_s ; I_s], H_s the
+  normalized s x s Hadamard matrix (Sylvester recursion
+  H_n = [[H_{n/2}, H_{n/2}], [H_{n/2}, -H_{n/2}]], H_2 = [[1, 1], [1, -1]],
+  normalized by 1/sqrt(n));
+* C in R^{2n x 2n}: diagonal, independent standard Cauchys;
+* B in R^{r1 x 2n}: each column an independent uniform standard basis vector;
+* the factor 4.
+
+Readings taken here (each is listed with its reason in the design notes):
+
+* n need not be a multiple of s: X is padded with zero rows to
+  n' = s * ceil(n / s);
+* inside block beta the H-half rows come first: stacked position
+  2 s beta + t holds (H_s z_beta)_t and 2 s beta + s + t holds (z_beta)_t;
+* an optional random sign diagonal D (row j multiplied by D(j)) is applied
+  before H~; with ``sign_flip=False`` Pi1 is exactly the paper's.
+
+``pi1_apply`` computes Pi1 X with a butterfly Walsh-Hadamard transform and
+per-column bucket sums; ``pi1_dense`` builds Pi1 as an explicit matrix for
+tiny n from the Kronecker recursion.  They share only the random streams.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import philox
+
+
+def hadamard_sylvester(s: int) -> np.ndarray:
+    """Normalized s x s Hadamard matrix from the Sylvester recursion (FCT1 section)."""
+    if s < 1 or s & (s - 1):
+        raise ValueError("s must be a power of two")
+    h = np.array([[1.0]])
+    h2 = np.array([[1.0, 1.0], [1.0, -1.0]])
+    while h.shape[0] < s:
+        h = np.kron(h2, h)          # [[H, H], [H, -H]]
+    return h / np.sqrt(s)
+
+
+def fwht_blocks(z: np.ndarray) -> np.ndarray:
+    """Normalized Walsh-Hadamard transform along axis 1 of z (nb, s, q).
+
+    Radix-2 butterflies in Sylvester (natural) order: at span h, entries i and
+    i + h of every 2h-group become (a + b, a - b).  Divided by sqrt(s) once.
+    """
+    z = np.array(z, dtype=np.float64, copy=True)
+    nb, s, q = z.shape
+    h = 1
+    while h < s:
+        v = z.reshape(nb, s // (2 * h), 2, h, q)
+        a = v[:, :, 0].copy()
+        b = v[:, :, 1]
+        v[:, :, 0] = a + b
+        v[:, :, 1] = a - b
+        h *= 2
+    return z / np.sqrt(s)
+
+
+def padded_rows(n: int, s: int) -> int:
+    return s * ((n + s - 1) // s)
+
+
+def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
+              instance: int = 0, cauchy_one: bool = False, return_scale: bool = False):
+    """Y = Pi1 X in FP64 for X of shape (n, q).
+
+    ``cauchy_one`` replaces every Cauchy by 1 (used by conservation pins).
+    ``return_scale`` also returns S_i = max_j sum_{k: h(k)=i} |4 C(k) g_kj|,
+    the l1 mass each output row accumulates, the scale that the GPU result
+    is compared against.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    n, q = X.shape
+    n_pad = padded_rows(n, s)
+    nb = n_pad // s
+    z = np.zeros((n_pad, q))
+    z[:n] = X
+    if sign_flip:
+        z *= philox.signs(seed, n_pad, instance)[:, None]
+    hz = fwht_blocks(z.reshape(nb, s, q)).reshape(n_pad, q)
+    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, instance)
+    if cauchy_one:
+        cH = np.ones_like(cH)
+        cI = np.ones_like(cI)
+    Y = np.zeros((r1, q))
+    S = np.zeros((r1, q))
+    for col in range(q):
+        gH = 4.0 * cH * hz[:, col]
+        gI = 4.0 * cI * z[:, col]
+        Y[:, col] = (np.bincount(hH, weights=gH, minlength=r1)
+                     + np.bincount(hI, weights=gI, minlength=r1))
+        if return_scale:
+            S[:, col] = (np.bincount(hH, weights=np.abs(gH), minlength=r1)
+                         + np.bincount(hI, weights=np.abs(gI), minlength=r1))
+    if return_scale:
+        return Y, S.max(axis=1)
+    return Y
+
+
+def pi1_dense(n: int, s: int, r1: int, seed: int, sign_flip: bool = True,
+              instance: int = 0) -> np.ndarray:
+    """Pi1 = 4 B C H~ D as an explicit r1 x n matrix (tiny n only)."""
+    n_pad = padded_rows(n, s)
+    nb = n_pad // s
+    Hs = hadamard_sylvester(s)
+    G = np.vstack([Hs, np.eye(s)])                      # G_s = [H_s; I_s]
+    Ht = np.zeros((2 * n_pad, n_pad))
+    for beta in range(nb):
+        Ht[2 * s * beta: 2 * s * (beta + 1), s * beta: s * (beta + 1)] = G
+    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, instance)
+    bucket = np.empty(2 * n_pad, dtype=np.int64)
+    cauchy = np.empty(2 * n_pad)
+    for beta in range(nb):
+        rows = np.arange(s * beta, s * (beta + 1))
+        bucket[2 * s * beta + np.arange(s)] = hH[rows]
+        cauchy[2 * s * beta + np.arange(s)] = cH[rows]
+        bucket[2 * s * beta + s + np.arange(s)] = hI[rows]
+        cauchy[2 * s * beta + s + np.arange(s)] = cI[rows]
+    B = np.zeros((r1, 2 * n_pad))
+    B[bucket, np.arange(2 * n_pad)] = 1.0
+    C = np.diag(cauchy)
+    D = np.diag(philox.signs(seed, n_pad, instance) if sign_flip else np.ones(n_pad))
+    P = 4.0 * B @ C @ Ht @ D
+    return P[:, :n]

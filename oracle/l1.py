@@ -1,0 +1,134 @@
+"""Exact (weighted) l1 regression optima: the yardstick for every (1+eps) claim.
+
+Problem statement (Introduction, l1 regression): minimize ||A x - b||_1.  Step 8
+of the FastCauchyRegression figure solves the coreset problem
+min ||D A x - D b||_1 "using linear programming"; with weights w_i = D_ii this
+is min sum_i w_i |A_i x - b_i|.
+
+Routes, independent of one another:
+
+* ``lp``           -- the linear program min sum w (u + v) s.t. A x + u - v = b,
+                      u, v >= 0, solved by HiGHS;
+* ``brute_force``  -- an LP optimum is attained at a vertex, where d rows are
+                      interpolated exactly, so the minimum over all d-row
+                      subsets B of f(A_B^-1 b_B) is the optimum (tiny n only);
+* ``certify_vertex`` -- LP duality: x_B (interpolating the rows B) is optimal
+                      iff some y with y_i = w_i sign(r_i) off B and
+                      |y_i| <= w_i on B has A^T y = 0;
+* ``weighted_median`` / ``separable_optimum`` -- closed form when every row of
+                      A is a canonical vector (the paper's large-scale test
+                      design): the problem splits per coordinate and each
+                      coordinate's optimum is a weighted median.
+
+Test infrastructure only.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def objective(A, b, x, w=None) -> float:
+    r = np.asarray(A, dtype=np.float64) @ np.asarray(x, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    if w is None:
+        return float(np.abs(r).sum())
+    return float((np.asarray(w, dtype=np.float64) * np.abs(r)).sum())
+
+
+def brute_force(A, b, w=None):
+    """Exact optimum over all d-row interpolating subsets (n <= ~20, d <= 3)."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n, d = A.shape
+    best_x, best_f = None, np.inf
+    for B in itertools.combinations(range(n), d):
+        AB = A[list(B)]
+        if abs(np.linalg.det(AB)) < 1e-12 * max(1.0, np.abs(AB).max() ** d):
+            continue
+        x = np.linalg.solve(AB, b[list(B)])
+        f = objective(A, b, x, w)
+        if f < best_f:
+            best_f, best_x = f, x
+    return best_x, best_f
+
+
+def lp(A, b, w=None):
+    """Exact optimum by linear programming (HiGHS)."""
+    import scipy.optimize
+    import scipy.sparse as sp
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n, d = A.shape
+    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
+    c = np.concatenate([np.zeros(d), w, w])
+    eye = sp.identity(n, format="csr")
+    A_eq = sp.hstack([sp.csr_matrix(A), eye, -eye], format="csr")
+    bounds = [(None, None)] * d + [(0, None)] * (2 * n)
+    res = scipy.optimize.linprog(c, A_eq=A_eq, b_eq=b, bounds=bounds, method="highs")
+    if res.status != 0:
+        raise RuntimeError(f"LP failed: {res.message}")
+    x = res.x[:d]
+    return x, objective(A, b, x, w)
+
+
+def certify_vertex(A, b, x_start, w=None, tol: float = 1e-9):
+    """Polish x_start to a vertex and test it with the LP dual.
+
+    Returns (x_vertex, f(x_vertex), optimal, dual_lower_bound).  B is taken as
+    the d rows of smallest |residual| that are linearly independent.  The
+    dual y is scaled into the box if needed, giving the lower bound
+    b^T y / ... = sum y_i b_i (valid for any feasible dual).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n, d = A.shape
+    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
+    r = A @ np.asarray(x_start, dtype=np.float64) - b
+    order = np.argsort(np.abs(r), kind="stable")
+    B = []
+    for i in order:
+        cand = B + [int(i)]
+        if np.linalg.matrix_rank(A[cand], tol=1e-10 * max(1.0, np.abs(A[cand]).max())) == len(cand):
+            B = cand
+        if len(B) == d:
+            break
+    if len(B) < d:
+        return np.asarray(x_start, dtype=np.float64), objective(A, b, x_start, w), False, -np.inf
+    AB = A[B]
+    xv = np.linalg.solve(AB, b[B])
+    r = A @ xv - b
+    inB = np.zeros(n, dtype=bool)
+    inB[B] = True
+    y = np.where(inB, 0.0, w * np.sign(r))
+    rhs = -(A[~inB].T @ y[~inB])
+    yB = np.linalg.solve(AB.T, rhs)
+    y[B] = yB
+    ratio = np.max(np.abs(yB) / w[B]) if d else 0.0
+    optimal = bool(ratio <= 1.0 + tol)
+    # A^T y = 0 holds by construction; scale into the box |y_i| <= w_i.
+    ys = y / max(1.0, ratio)
+    # weak duality: for A^T y = 0 and |y_i| <= w_i, sum w|r| >= -sum y_i b_i
+    lower = float(-(ys @ b))
+    return xv, objective(A, b, xv, w), optimal, lower
+
+
+def weighted_median(values, weights=None) -> float:
+    """A minimizer of sum_i w_i |x - v_i| (lower weighted median)."""
+    v = np.asarray(values, dtype=np.float64)
+    wt = np.ones_like(v) if weights is None else np.asarray(weights, dtype=np.float64)
+    order = np.argsort(v, kind="stable")
+    cw = np.cumsum(wt[order])
+    k = int(np.searchsorted(cw, 0.5 * cw[-1]))
+    return float(v[order][k])
+
+
+def separable_optimum(coord, b, d: int, w=None) -> np.ndarray:
+    """Optimum when row i of A is the canonical vector e_{coord[i]}."""
+    coord = np.asarray(coord)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(d)
+    for c in range(d):
+        sel = coord == c
+        x[c] = weighted_median(b[sel], None if w is None else np.asarray(w)[sel])
+    return x

@@ -1,0 +1,52 @@
+"""The whole FastCauchyRegression path (figure l1reg-mainSimp), plainly.
+
+Steps, in the paper's order:
+
+1. X = [A, -b], Pi1 the FCT1 transform;
+2. X' = Pi1 X and its QR factorization (R, positive diagonal);
+3. Pi2 (q x r2) of independent Cauchys;
+4. Lambda = X R^-1 Pi2, computed as X (R^-1 Pi2);
+5. lambda_i = median_j |Lambda_ij|;
+6. p_i = min{1, s lambda_i / sum lambda};
+7. D_ii = 1/p_i with probability p_i;
+8. x_hat = argmin ||D A x - D b||_1 by linear programming.
+
+Test infrastructure only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import basis, fct, l1, lowp, sampling
+
+
+def form_x(A, b=None) -> np.ndarray:
+    A = np.asarray(A, dtype=np.float64)
+    if b is None:
+        return A
+    return np.hstack([A, -np.asarray(b, dtype=np.float64)[:, None]])
+
+
+def l1_regress(A, b, s: int, r1: int, r2: int, s_out: float, seed: int,
+               sign_flip: bool = True, lowp_pass2: bool = False, solve: bool = True):
+    """Run steps 1-8; return every intermediate in a dict."""
+    X = form_x(A, b)
+    Y = fct.pi1_apply(X, s, r1, seed, sign_flip=sign_flip)
+    R = basis.qr_r(Y)
+    M = basis.m_matrix(R, seed, r2)
+    if lowp_pass2:
+        Xl = lowp.round_bf16(np.asarray(X, dtype=np.float32))
+        Ml = lowp.round_bf16(np.asarray(M, dtype=np.float32))
+        lam = sampling.row_norm_estimates(Xl, Ml)
+    else:
+        lam = sampling.row_norm_estimates(X, M)
+    total = float(lam.sum())
+    p = sampling.probabilities(lam, s_out, total)
+    idx, w = sampling.select(p, seed)
+    out = dict(X=X, Y=Y, R=R, M=M, lam=lam, sum_lambda=total, p=p, idx=idx, w=w)
+    if solve:
+        A64 = np.asarray(A, dtype=np.float64)
+        b64 = np.asarray(b, dtype=np.float64)
+        x_hat, f_core = l1.lp(A64[idx], b64[idx], w)
+        out.update(x=x_hat, coreset_objective=f_core, objective=l1.objective(A64, b64, x_hat))
+    return out
