@@ -1,0 +1,166 @@
+"""Benchmark of the FastCauchyRegression hot path on one MI355X.
+
+A step is one whole pass of the path over the tall workload
+(4,194,304 x 32 FP32, s = 256, r1 = 2048, r2 = 16, s_out = 8000): the FCT1
+sketch (pass 1), the FP64 QR, the row-norm pass (pass 2), the Bernoulli
+selection, the gather and the FP64 coreset solve, all through l1_regress.
+Inputs are resident in HBM before the timed region.
+
+value = algorithmic bytes of the two streaming passes (X read twice, lambda
+written once) per step / step time.  The dominant kernel's roofline entry
+uses the pass-1 kernel's own device time, measured with HIP events around its
+launches on the stream it runs on.  The CPU oracle is timed on a bounded
+sample of the same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Π1A + sampling pass GB/s (% HBM peak); ℓ1 solve time at (1+ε) opt, plain vs BF16"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_oracle_sample(A, b, w, rows: int):
+    """Time the oracle's steps 1-7 on the first `rows` rows, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import basis, fct, pipeline, sampling
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        X = pipeline.form_x(A[:, :rows].T, b[:rows])
+        Y = fct.pi1_apply(X, w.s, w.r1, w.seed)
+        R = basis.qr_r(Y)
+        M = basis.m_matrix(R, w.seed, w.r2)
+        lam = sampling.row_norm_estimates(X, M)
+        p = sampling.probabilities(lam, w.s_out)
+        sampling.select(p, w.seed)
+        dt = time.perf_counter() - t0
+    q = w.d + 1
+    nbytes = 2 * rows * q * 4 + rows * 4
+    return dict(value=nbytes / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample=f"first {rows} of {w.n} rows, steps 1-7 (sketch, QR, row norms, selection), "
+                       f"{dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 21)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "design (row shards, one all-reduce of the r1 x q sketch) is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1207_4684_amd import fctl1 as F
+
+    w = synth.TALL
+    q = w.d + 1
+    A, b, _ = synth.generate(w)
+    Ad = torch.from_numpy(A).cuda()
+    bd = torch.from_numpy(b).cuda()
+    ctx = F.Context(0)
+    Al = F.fct_to_bf16(ctx, Ad)
+    bl = F.fct_to_bf16(ctx, bd)
+    torch.cuda.synchronize()
+    prm = F.params(s=w.s, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
+
+    def step(lowp: bool):
+        if lowp:
+            return F.l1_regress(ctx, Ad, bd, prm, eps=w.eps, A_lowp=Al, b_lowp=bl)
+        return F.l1_regress(ctx, Ad, bd, prm, eps=w.eps)
+
+    def timed(lowp: bool, steps: int):
+        for _ in range(args.warmup):
+            step(lowp)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = step(lowp)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        prof = [ctx.profile_read(k) for k in range(3)]
+        ctx.profile(False)
+        return dt, prof, out
+
+    dt_plain, prof_plain, (x_plain, _, S_plain) = timed(False, args.steps)
+    dt_bf16, prof_bf16, (x_bf16, _, S_bf16) = timed(True, args.steps)
+
+    pass1_bytes = w.n * q * 4
+    pass2_bytes = w.n * q * 4 + w.n * 4
+    pass2_bytes_bf16 = w.n * q * 2 + w.n * 4
+    p1_ms = prof_plain[0][0] / max(1, prof_plain[0][1])
+    p2_ms = prof_plain[1][0] / max(1, prof_plain[1][1])
+    p2b_ms = prof_bf16[1][0] / max(1, prof_bf16[1][1])
+    solve_ms = prof_plain[2][0] / max(1, prof_plain[2][1])
+    p1_gbs = pass1_bytes / (p1_ms * 1e-3) / 1e9
+    value = (pass1_bytes + pass2_bytes) / dt_plain / 1e9
+
+    f_plain = F.fct_l1_objective(ctx, Ad, bd, x_plain)
+    f_bf16 = F.fct_l1_objective(ctx, Ad, bd, x_bf16)
+    ref = None
+    if not args.skip_ref:
+        x_ref, _ = F.l1_solve(ctx, Ad, bd, torch.ones(w.n, dtype=torch.float64, device="cuda"),
+                              iters=120)
+        ref = F.fct_l1_objective(ctx, Ad, bd, x_ref)
+
+    cpu = None if args.skip_cpu else cpu_oracle_sample(A, b, w, args.cpu_rows)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt_plain * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "s": w.s, "r1": w.r1, "r2": w.r2,
+                   "s_out": w.s_out, "eps": w.eps, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(p1_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(p1_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "pass1_kernel (FCT1 sketch)", "kernel_ms": round(p1_ms, 5)},
+        "cpu_baseline": cpu,
+        "passes": {
+            "pass1_ms": round(p1_ms, 5), "pass1_GBps": round(p1_gbs, 1),
+            "pass2_f32_ms": round(p2_ms, 5),
+            "pass2_f32_GBps": round(pass2_bytes / (p2_ms * 1e-3) / 1e9, 1),
+            "pass2_bf16_ms": round(p2b_ms, 5),
+            "pass2_bf16_GBps": round(pass2_bytes_bf16 / (p2b_ms * 1e-3) / 1e9, 1),
+            "solve_ms": round(solve_ms, 4),
+        },
+        "end_to_end": {
+            "plain_ms": round(dt_plain * 1e3, 4), "bf16_ms": round(dt_bf16 * 1e3, 4),
+            "coreset_rows_plain": S_plain, "coreset_rows_bf16": S_bf16,
+            "objective_plain": f_plain, "objective_bf16": f_bf16,
+            "objective_all_rows_solve": ref,
+            "ratio_plain": (f_plain / ref) if ref else None,
+            "ratio_bf16": (f_bf16 / ref) if ref else None,
+        },
+    }
+    ctx.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * fctl1 -- Fast Cauchy Transform l1 regression on AMD MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of FastCauchyRegression (Clarkson,
+ * Drineas, Magdon-Ismail, Mahoney, Meng, Woodruff, "The Fast Cauchy Transform
+ * and Faster Robust Linear Regression", arXiv 1207.4684):
+ *
+ *   fct_sketch       Pi1 X with the FCT1 transform Pi1 = 4 B C H~
+ *                    (Section "FCT1 Construction"), optional FP64 R of its QR
+ *                    (figure FastL1Basis; regression figure steps 1-2);
+ *   l1_sample_probs  lambda_i = median_j |(X R^-1 Pi2)_ij| and
+ *                    p_i = min{1, s lambda_i / sum lambda} (steps 3-6);
+ *   l1_coreset       steps 1-7: the kept rows, their weights 1/p_i and the
+ *                    gathered coreset (D A, D b) without the weights applied;
+ *   l1_regress       steps 1-8: x_hat = argmin ||D A x - D b||_1 (step 8 by
+ *                    FP64 iteratively reweighted least squares on the GPU).
+ *
+ * Conventions shared by every entry point:
+ *   - X = [A, -b] has n rows and q = d + 1 columns when b != NULL, else X = A
+ *     and q = d.  A is column-major: element (i, j) at A[i + j * lda], lda >= n.
+ *     b is a length-n vector of the same type.  All array arguments are DEVICE
+ *     pointers unless marked "host"; the caller owns every buffer it passes.
+ *   - The library owns only the scratch memory inside its context.
+ *   - Every call is enqueued on the context's HIP stream; a call with host
+ *     outputs waits for the stream before it returns.
+ *   - Arguments are checked before anything is launched; on an error no output
+ *     is written.  Status codes are the FCT_* values below (0 = success); no
+ *     C++ exception crosses the interface.
+ *   - Random quantities come from Philox4x32-10 with key = seed and counters
+ *     (index, 0, stream, 0) as listed in the design notes; the same seed gives
+ *     the same Pi1, Pi2 and sampling decisions as the CPU oracle.
+ *   - Floating-point sums inside a sketch are accumulated in LDS with atomic
+ *     adds, so repeated runs agree to rounding, not bit for bit.  Integer and
+ *     index outputs (RNG words, buckets, signs, selected rows given the same
+ *     probabilities) are exact.
+ */
+#ifndef FCTL1_H
+#define FCTL1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fct_ctx fct_ctx;
+
+typedef enum { FCT_F32 = 0, FCT_F64 = 1, FCT_BF16 = 2 } fct_dtype;
+
+enum {
+  FCT_OK = 0,
+  FCT_ERR_BAD_ARG = -1,        /* an argument is out of range or NULL         */
+  FCT_ERR_OOM = -2,            /* device scratch could not be allocated        */
+  FCT_ERR_NONFINITE = -3,      /* NaN or Inf met in an input                   */
+  FCT_ERR_RANK_DEFICIENT = -4, /* |R_jj| <= tol ||R[:, j]||_2 (tol 1e-13 for FP64 input,
+                                  1e-5 for FP32), or a singular coreset system  */
+  FCT_ERR_HIP = -5,            /* a HIP runtime call failed                    */
+  FCT_ERR_CAPACITY = -6        /* realised coreset size exceeds the capacity   */
+};
+
+/* Flags of fct_params.flags and of fct_sketch. */
+#define FCT_FLAG_NO_SIGN_FLIP 1u /* Pi1 without the random sign diagonal: the paper's Pi1 exactly */
+
+typedef struct {
+  int32_t s;      /* FWHT block size: power of two in [2, 4096]                  */
+  int32_t r1;     /* rows of Pi1 (sketch rows), q <= r1 <= 65536                 */
+  int32_t r2;     /* columns of Pi2, 1 <= r2 <= 32                               */
+  int32_t pad0;
+  int64_t s_out;  /* expected coreset size: the paper's s in step 6 (> 0)        */
+  uint64_t seed;  /* key of every random stream                                  */
+  uint32_t flags; /* FCT_FLAG_*                                                   */
+  int32_t irls_iters; /* step 8 iteration cap (<= 0: library default)            */
+} fct_params;
+
+/* Context: binds a device and a HIP stream (hip_stream == NULL: the library
+ * creates its own stream).  *ctx receives the handle.  Status code. */
+int fct_create(fct_ctx **ctx, int device, void *hip_stream);
+/* Frees the context's scratch and stream (if it created it). NULL is a no-op. */
+void fct_destroy(fct_ctx *ctx);
+/* Static text for a status code. */
+const char *fct_strerror(int status);
+/* Waits for all work queued on the context's stream and returns (then clears)
+ * the first condition the device flagged since the last wait:
+ * FCT_ERR_NONFINITE or FCT_ERR_RANK_DEFICIENT; FCT_OK otherwise. */
+int fct_sync(fct_ctx *ctx);
+/* The HIP stream the context enqueues on (hipStream_t as void*). */
+void *fct_stream(fct_ctx *ctx);
+
+/*
+ * fct_sketch: Y = Pi1 X (FCT1 section; regression figure step 2).
+ *   A, lda, b  as above; dt = FCT_F32 or FCT_F64 (A and b of that type).
+ *   n >= 1, 1 <= d, q <= r1; s a power of two in [2, 4096]; rows are padded
+ *   with zeros to s * ceil(n / s).
+ *   Y: device, r1 x q column-major (ld = r1), of type dt.  May be NULL when
+ *      only R is wanted.
+ *   R: device, q x q column-major FP64, upper triangular with positive
+ *      diagonal, Pi1 X = Q R (may be NULL).  Requires q <= 88.
+ *   flags: FCT_FLAG_NO_SIGN_FLIP or 0.
+ *   Conditions found on the device (a non-finite input, a rank-deficient
+ *   sketch) are reported by the next fct_sync on the context (the call
+ *   itself does not wait): FCT_ERR_NONFINITE, FCT_ERR_RANK_DEFICIENT.
+ */
+int fct_sketch(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda, fct_dtype dt,
+               const void *b, int32_t s, int32_t r1, uint64_t seed, uint32_t flags,
+               void *Y, double *R);
+
+/*
+ * l1_sample_probs: steps 3-6 of the regression figure.
+ *   M = R^-1 Pi2 (q x r2, Pi2 of independent Cauchys from the seed) is formed
+ *   on the device in FP64, then X is streamed once:
+ *   lambda_i = median_j |(X M)_ij| (median of an even count = mean of the two
+ *   middle values) and sum_lambda = sum_i lambda_i (FP64).
+ *   dt = FCT_F32 or FCT_F64: A and b of that type, contraction in that type.
+ *   dt = FCT_BF16: A and b are BF16 copies (same layout); the contraction runs
+ *   on bf16 matrix cores with FP32 accumulation and M rounded to BF16.
+ *   R: device q x q FP64 from fct_sketch.  1 <= r2 <= 32.  s_out > 0.
+ *   lambda: device FP32 [n] or NULL; p: device FP32 [n] (p_i rounded to FP32)
+ *   or NULL; sum_lambda: device FP64 scalar or NULL.
+ */
+int l1_sample_probs(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
+                    int64_t lda, fct_dtype dt, const double *R, int32_t r2, uint64_t seed,
+                    int64_t s_out, float *lambda, float *p, double *sum_lambda);
+
+/*
+ * l1_coreset: steps 1-7.  Row i is kept iff its stream-3 word is below
+ * floor(p_i 2^32) (p_i formed in FP64); kept rows are listed in ascending
+ * order.
+ *   A, b, dt (FCT_F32 or FCT_F64): the original data, also gathered from.
+ *   A_lowp, b_lowp, ld_lowp: optional BF16 copies of A and b streamed by the
+ *   sampling pass (NULL: the sampling pass streams A and b).
+ *   prm: s, r1, r2, s_out, seed, flags.  cap: capacity in rows of the outputs.
+ *   At: device, cap x d column-major (ld = cap), type dt: rows A_idx (unscaled).
+ *   bt: device [cap], type dt.  w: device FP64 [cap], 1/p_i.  idx: device
+ *   int64 [cap].  S: host, the realised count.  If S > cap the call returns
+ *   FCT_ERR_CAPACITY with *S set and the first cap rows written.
+ */
+int l1_coreset(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d, int64_t lda,
+               fct_dtype dt, const void *A_lowp, const void *b_lowp, int64_t ld_lowp,
+               const fct_params *prm, int64_t cap, void *At, void *bt, double *w, int64_t *idx,
+               int64_t *S);
+
+/*
+ * l1_regress: the whole method.  eps documents the acceptance target; when
+ * prm->s_out <= 0 the expected coreset size is ceil(20 q / eps).
+ *   x: host double[d], the minimizer of the weighted coreset objective.
+ *   obj: host double or NULL, the coreset objective sum_k w_k |A_k x - b_k|.
+ *   S_out: host int64 or NULL, the realised coreset size.
+ */
+int l1_regress(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d, int64_t lda,
+               fct_dtype dt, const void *A_lowp, const void *b_lowp, int64_t ld_lowp, double eps,
+               const fct_params *prm, double *x, double *obj, int64_t *S_out);
+
+/*
+ * l1_select: steps 6-7 alone, from row-norm estimates already computed
+ * (l1_sample_probs): p_i = min{1, s_out lambda_i / sum_lambda} in FP64 and
+ * row i kept iff its stream-3 word is below floor(p_i 2^32).  Several draws
+ * from one sampling pass use different seeds.
+ *   lambda: device FP32 [n]; sum_lambda: device FP64 scalar.
+ *   idx: device int64 [cap], ascending; w: device FP64 [cap], 1/p_i.
+ *   S: host, realised count; FCT_ERR_CAPACITY when S > cap (first cap written).
+ */
+int l1_select(fct_ctx *ctx, const float *lambda, const double *sum_lambda, int64_t n,
+              int64_t s_out, uint64_t seed, int64_t cap, int64_t *idx, double *w, int64_t *S);
+
+/* ---- supporting calls (diagnostics and data preparation) ---------------- */
+
+/* words: device uint32 [4 * count], the Philox4x32-10 words of calls
+ * idx0 .. idx0 + count - 1 of `stream` (0..3) under `seed`, instance 0. */
+int fct_rng_words(fct_ctx *ctx, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
+                  uint32_t *words);
+
+/* Per padded row j in [j0, j0 + count): bucket_h, cauchy_h, bucket_i,
+ * cauchy_i (stream 0) and sign (stream 1), as the sketch kernels compute
+ * them.  Device outputs, each of length count; sign is +1/-1 as int8. */
+int fct_pi1_streams(fct_ctx *ctx, uint64_t seed, int32_t r1, uint64_t j0, int64_t count,
+                    int32_t *bucket_h, float *cauchy_h, int32_t *bucket_i, float *cauchy_i,
+                    int8_t *sign);
+
+/* In-place normalized Walsh-Hadamard transform (Sylvester order) of every
+ * consecutive block of s values of x (device FP32 [nblocks * s]), with the
+ * kernel the sketch uses.  s power of two in [2, 4096]. */
+int fct_fwht(fct_ctx *ctx, float *x, int64_t nblocks, int32_t s);
+
+/* Kernel timing: enable != 0 starts recording HIP events around every
+ * pass-1 kernel (kind 0), pass-2 kernel (kind 1) and step-8 solve sequence
+ * (kind 2) launched on the context's stream (up to 512 of each; counts are
+ * reset); 0 stops.  fct_profile_read waits for the stream and returns the
+ * summed device milliseconds and the number of launches of `kind`. */
+int fct_profile(fct_ctx *ctx, int enable);
+int fct_profile_read(fct_ctx *ctx, int kind, double *total_ms, int64_t *count);
+
+/* BF16 copy (round to nearest even) of a device FP32 array. */
+int fct_to_bf16(fct_ctx *ctx, const float *x, int64_t count, uint16_t *y);
+
+/* sum_i |A_i x - b_i| over all n rows (device reduction, FP64 result).
+ * x: host double[d]; out: host double. */
+int fct_l1_objective(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d, int64_t lda,
+                     fct_dtype dt, const double *x, double *out);
+
+/* Weighted l1 solve of step 8 alone: x = argmin sum_k w_k |At_k x - bt_k|
+ * on a device coreset (At: S x d column-major, ld = ldat; bt, w device).
+ * x: host double[d]; obj: host double or NULL. */
+int l1_solve(fct_ctx *ctx, const void *At, const void *bt, const double *w, int64_t S, int32_t d,
+             int64_t ldat, fct_dtype dt, int32_t iters, double *x, double *obj);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCTL1_H */

@@ -69,9 +69,12 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
     """Y = Pi1 X in FP64 for X of shape (n, q).
 
     ``cauchy_one`` replaces every Cauchy by 1 (used by conservation pins).
-    ``return_scale`` also returns S_i = max_j sum_{k: h(k)=i} |4 C(k) g_kj|,
-    the l1 mass each output row accumulates, the scale that the GPU result
-    is compared against.
+    ``return_scale`` also returns, per output row i, the l1 mass of the fully
+    expanded sum that forms it: S_i = max_j sum_{k: h(k)=i} 4 |C(k)| (|G_s| |z|)_kj,
+    where |G_s| |z| is sum_v |z_v| / sqrt(s) on the H-half and |z_t| on the
+    I-half.  Rounding errors of any evaluation order are bounded relative to
+    this scale (a reading of "relative to each output row's scale": |Y_ij|
+    itself can cancel, and so can a single (H_s z)_t).
     """
     X = np.asarray(X, dtype=np.float64)
     n, q = X.shape
@@ -88,13 +91,15 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
         cI = np.ones_like(cI)
     Y = np.zeros((r1, q))
     S = np.zeros((r1, q))
+    if return_scale:
+        absmass = np.repeat(np.abs(z).reshape(nb, s, q).sum(axis=1), s, axis=0) / np.sqrt(s)
     for col in range(q):
         gH = 4.0 * cH * hz[:, col]
         gI = 4.0 * cI * z[:, col]
         Y[:, col] = (np.bincount(hH, weights=gH, minlength=r1)
                      + np.bincount(hI, weights=gI, minlength=r1))
         if return_scale:
-            S[:, col] = (np.bincount(hH, weights=np.abs(gH), minlength=r1)
+            S[:, col] = (np.bincount(hH, weights=4.0 * np.abs(cH) * absmass[:, col], minlength=r1)
                          + np.bincount(hI, weights=np.abs(gI), minlength=r1))
     if return_scale:
         return Y, S.max(axis=1)

@@ -113,6 +113,48 @@ def certify_vertex(A, b, x_start, w=None, tol: float = 1e-9):
     return xv, objective(A, b, xv, w), optimal, lower
 
 
+def dual_lower_bound(A, b, x, w=None):
+    """A certified lower bound on min_x sum_i w_i |A_i x - b_i| (weak LP duality).
+
+    For any y with A^T y = 0 and |y_i| <= w_i, and any x,
+    sum_i w_i |r_i(x)| >= sum_i y_i r_i(x) = -y^T b.  y is built from a
+    candidate x: y_i = w_i clip(r_i / tau, -1, 1) (the subgradient of the
+    l1 term, smoothed on |r| <= tau); the violation A^T y is removed by the
+    minimum-norm correction supported on the free rows F = {|r_i| < tau}
+    (rows whose y_i is inside the box), and y is finally scaled into the box.
+    At a vertex with tau between the d interpolated residuals and the rest,
+    F is the basis and this is the classical certificate.  Several tau are
+    tried; the best bound is returned.  Valid whatever produced x (up to the
+    rounding of A^T y = 0); tight when x is optimal.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n, d = A.shape
+    w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
+    r = A @ np.asarray(x, dtype=np.float64) - b
+    ar = np.sort(np.abs(r))
+    scale_r = float(ar[-1]) or 1.0
+    ranks = [ar[min(n - 1, k)] * 1.0001 for k in (d - 1, d, 2 * d, 4 * d)]
+    taus = sorted(set(np.concatenate([scale_r * 10.0 ** np.arange(-16.0, 0.5, 0.5), ranks])))
+    best = -np.inf
+    for tau in taus:
+        if not tau > 0:
+            continue
+        y = w * np.clip(r / tau, -1.0, 1.0)
+        free = np.abs(r) < tau
+        if free.sum() < d:
+            continue
+        AF = A[free]
+        g = A.T @ y
+        delta, *_ = np.linalg.lstsq(AF.T, -g, rcond=None)
+        y[free] += delta
+        if np.linalg.norm(A.T @ y) > 1e-9 * (np.abs(A).T @ np.abs(y)).max():
+            continue
+        sc = max(1.0, float(np.max(np.abs(y) / w)))
+        best = max(best, float(-(y / sc) @ b))
+    return best
+
+
 def weighted_median(values, weights=None) -> float:
     """A minimizer of sum_i w_i |x - v_i| (lower weighted median)."""
     v = np.asarray(values, dtype=np.float64)

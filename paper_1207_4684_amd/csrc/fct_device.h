@@ -1,0 +1,107 @@
+// Device-side building blocks shared by the fctl1 kernels (gfx950, wave64).
+//
+// Random streams: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): a
+// 128-bit counter, a 64-bit key, ten rounds of two 32x32->64-bit products
+// with the multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule
+// 0x9E3779B9 / 0xBB67AE85.  Stream layout (key = seed, counter =
+// (idx lo, idx hi, stream, instance)):
+//   stream 0: idx = padded row j -> (bucket_H, cauchy_H, bucket_I, cauchy_I)
+//             of the two stacked positions of row j (FCT1: columns of B and
+//             diagonal of C);
+//   stream 1: idx = j >> 7, bit j & 31 of word (j >> 5) & 3 -> sign D(j);
+//   stream 2: idx = a * r2 + c, word 0 -> Pi2[a][c];
+//   stream 3: idx = i >> 2, word i & 3 -> uniform deciding row i.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fctl1 {
+
+enum : uint32_t { kStreamPi1 = 0, kStreamSign = 1, kStreamPi2 = 2, kStreamSample = 3 };
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint4 stream_words(uint64_t seed, uint32_t stream, uint64_t idx,
+                                              uint32_t instance) {
+  return philox4x32_10(make_uint4((uint32_t)idx, (uint32_t)(idx >> 32), stream, instance),
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// Uniform bucket in [0, r1): floor(w * r1 / 2^32).
+__device__ __forceinline__ uint32_t bucket_from_word(uint32_t w, uint32_t r1) {
+  return __umulhi(w, r1);
+}
+
+// Standard Cauchy variate from a 32-bit word, FP32: the inverse CDF
+// tan(pi (u - 1/2)) with u = (w + 1/2) / 2^32, evaluated without
+// cancellation.  With m = min(w, 2^32 - 1 - w) the value is -/+ cot(pi v),
+// v = (m + 1/2) / 2^32 in (0, 1/2) (minus for w < 2^31).  The argument is
+// reduced to x = pi v' in (0, pi/4]: for v < 1/4, cot(pi v) = cos x / sin x
+// with v' = v; otherwise cot(pi v) = tan(pi (1/2 - v)) = sin x / cos x with
+// v' = 1/2 - v, whose numerator 2^31 - 1 - m + 1/2 is formed exactly in
+// integers.  sin and cos come from their Taylor series in x^2 (terms to x^9
+// and x^10: truncation below 2e-9 relative on (0, pi/4]); the argument is
+// formed from an exact 22-bit/8-bit split of the integer numerator and a
+// two-term FP32 split of pi 2^-32.
+__device__ __forceinline__ float cauchy_from_word(uint32_t w) {
+  const bool neg = w < 0x80000000u;
+  const uint32_t m = neg ? w : ~w;                   // < 2^31
+  const bool lower = m < 0x40000000u;                // v < 1/4
+  const uint32_t mr = lower ? m : (0x7FFFFFFFu - m); // < 2^30
+  const float hi = (float)(mr >> 8) * 256.0f;        // exact
+  const float lo = (float)(mr & 0xFFu) + 0.5f;       // exact
+  const float K1 = 0x1.921fb6p-31f;                  // pi * 2^-32, FP32 head
+  const float K2 = -0x1.777a5cp-56f;                 // remainder, FP32 tail
+  const float x = fmaf(hi, K1, fmaf(hi, K2, lo * K1));
+  const float x2 = x * x;
+  float sn = fmaf(x2, 0x1.71de3ap-19f, -0x1.a01a02p-13f); // 1/9!, -1/7!
+  sn = fmaf(x2, sn, 0x1.111112p-7f);                      // 1/5!
+  sn = fmaf(x2, sn, -0x1.555556p-3f);                     // -1/3!
+  sn = x * fmaf(x2, sn, 1.0f);
+  float cs = fmaf(x2, -0x1.27e4fcp-22f, 0x1.a01a02p-16f); // -1/10!, 1/8!
+  cs = fmaf(x2, cs, -0x1.6c16c2p-10f);                    // -1/6!
+  cs = fmaf(x2, cs, 0x1.555556p-5f);                      // 1/4!
+  cs = fmaf(x2, cs, -0.5f);
+  cs = fmaf(x2, cs, 1.0f);
+  const float num = lower ? cs : sn;
+  const float den = lower ? sn : cs;
+  const float c = num * __frcp_rn(den);
+  return neg ? -c : c;
+}
+
+// FP64 Cauchy for Pi2 (a few hundred values per regression).
+__device__ __forceinline__ double cauchy_from_word_f64(uint32_t w) {
+  const bool neg = w < 0x80000000u;
+  const uint32_t m = neg ? w : ~w;
+  const double v = ((double)m + 0.5) * 0x1p-32;
+  const double c = 1.0 / tan(3.141592653589793 * v);
+  return neg ? -c : c;
+}
+
+// sign D(j) of stream 1 as +1 / -1
+__device__ __forceinline__ float sign_from_words(uint4 wv, uint64_t j) {
+  const uint32_t sel = (uint32_t)(j >> 5) & 3u;
+  const uint32_t word = sel == 0 ? wv.x : sel == 1 ? wv.y : sel == 2 ? wv.z : wv.w;
+  return ((word >> (j & 31u)) & 1u) ? -1.0f : 1.0f;
+}
+
+template <typename T> struct FmaT;
+template <> struct FmaT<float> {
+  static __device__ __forceinline__ float fma(float a, float b, float c) { return fmaf(a, b, c); }
+};
+template <> struct FmaT<double> {
+  static __device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
+};
+
+}  // namespace fctl1

@@ -1,0 +1,118 @@
+// Internal interface between the C ABI (fctl1_api.hip) and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fctl1 {
+
+struct Pass1Args {
+  const void* A;
+  const void* b;       // NULL when X = A
+  int64_t lda;
+  int64_t n;           // rows
+  int64_t n_pad;       // s * ceil(n / s)
+  int64_t rows_per_range;
+  int32_t d;           // columns of A
+  int32_t q;           // columns of X
+  int32_t s;
+  int32_t log2s;
+  int32_t r1;
+  int32_t c;           // columns per slice (last slice may be narrower)
+  uint64_t seed;
+  uint32_t instance;
+  int32_t sign_flip;
+  void* partials;      // [nranges][q][r1] of the input type
+};
+
+struct Pass1Plan {
+  int threads;
+  int rpt;             // rows per thread per chunk
+  int c;
+  int nslices;
+  int nranges;
+  int64_t rows_per_range;
+  size_t lds;
+};
+
+hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStream_t st);
+hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
+                                  double* Yd, int* flag, bool f64, hipStream_t st);
+hipError_t launch_rng_words(uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
+                            uint32_t* out, hipStream_t st);
+hipError_t launch_pi1_streams(uint64_t seed, uint32_t r1, uint64_t j0, int64_t count, int32_t* bh,
+                              float* ch, int32_t* bi, float* ci, int8_t* sg, hipStream_t st);
+hipError_t launch_fwht(float* x, int64_t nblocks, int s, int log2s, hipStream_t st);
+
+// QR of the FP64 sketch (tall r1 x q, column-major, ld = r1) by a tree of
+// Householder panel factorizations.  work must hold qr_work_doubles(r1, q).
+size_t qr_work_doubles(int r1, int q);
+// rank_tol: R is rank deficient when some |R_jj| <= rank_tol * ||R[:, j]||_2
+// (the component of column j orthogonal to the earlier columns, relative to
+// the column's own norm).
+hipError_t launch_qr(const double* Y, int r1, int q, double* work, double* R, double rank_tol,
+                     int* status, hipStream_t st);
+// M = R^-1 Pi2 (q x r2), written row-major with row stride ldm >= r2 (zero
+// padding) as FP64, and when non-NULL as FP32 (Mf), as FP32 values of its
+// BF16 rounding (Mfb) and as BF16 bit patterns (Mb).
+hipError_t launch_form_m(const double* R, int q, int r2, int ldm, uint64_t seed,
+                         uint32_t instance, double* Md, float* Mf, float* Mfb, uint16_t* Mb,
+                         int* status, hipStream_t st);
+int r2_padded(int r2);
+
+// Pass 2: lambda and per-workgroup FP64 partial sums of lambda.
+struct Pass2Args {
+  const void* A;
+  const void* b;
+  int64_t lda;
+  int64_t n;
+  int32_t d;
+  int32_t q;
+  int32_t r2;
+  const void* M;       // q x r2_padded row-major: FP64 for FP64 data, else FP32
+                       // (the BF16-rounded values for the BF16 path)
+  const uint16_t* Mb;  // same layout, BF16 bits (BF16 path)
+  float* lambda;
+  double* wg_sums;     // [grid]
+};
+enum Pass2Kind { kPass2F32 = 0, kPass2F64 = 1, kPass2BF16 = 2 };
+int pass2_grid(int64_t n, int kind);
+hipError_t launch_pass2(const Pass2Args& a, int kind, hipStream_t st);
+hipError_t launch_sum_fixed(const double* parts, int count, double* out, hipStream_t st);
+
+// Selection: p_i = min(1, s_out lambda_i / sum), keep iff word_i < floor(p_i 2^32).
+struct SelectArgs {
+  const float* lambda;
+  const double* sum_lambda;
+  int64_t n;
+  double s_out;
+  uint64_t seed;
+  uint32_t instance;
+  float* p_out;        // optional
+  int32_t* counts;     // [grid]
+  int64_t* offsets;    // [grid + 1]
+  int64_t* idx;        // [cap]
+  double* w;           // [cap]
+  int64_t cap;
+  int64_t* S;          // device scalar
+};
+int select_grid(int64_t n);
+hipError_t launch_select(const SelectArgs& a, hipStream_t st);
+hipError_t launch_probs_only(const SelectArgs& a, hipStream_t st);
+
+// Gather the kept rows of A and b (unscaled) into column-major outputs.
+hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, const int64_t* idx,
+                         const int64_t* S, int64_t cap, void* At, void* bt, int64_t ldat, bool f64,
+                         hipStream_t st);
+
+// Step 8: weighted l1 solve by FP64 IRLS.
+size_t irls_work_doubles(int64_t S, int d);
+hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,
+                       int64_t cap, int d, int64_t ldat, bool f64, int iters, double* work,
+                       double* x_out, double* obj_out, int* status, hipStream_t st);
+
+hipError_t launch_to_bf16(const float* x, int64_t count, uint16_t* y, hipStream_t st);
+hipError_t launch_l1_objective(const void* A, const void* b, int64_t lda, int64_t n, int d,
+                               const double* x, bool f64, double* parts, int nparts, double* out,
+                               hipStream_t st);
+
+}  // namespace fctl1

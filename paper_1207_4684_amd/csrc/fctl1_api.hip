@@ -1,0 +1,727 @@
+// C ABI of fctl1 (declared in include/fctl1.h): argument checks, work plans,
+// scratch management and the launch sequences of the FastCauchyRegression
+// path (regression figure steps 1-8).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/fctl1.h"
+#include "fct_kernels.h"
+
+using namespace fctl1;
+
+struct fct_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  int* flags = nullptr;         // device: [0] non-finite, [1] rank / solve status
+  void* pinned = nullptr;       // host pinned staging for small readbacks
+  int cus = 256;
+  size_t lds_optin = 65536;
+  // optional per-kernel timing with HIP events on the context stream
+  static constexpr int kProfSlots = 512;
+  bool prof_on = false;
+  int prof_n[3] = {0, 0, 0};
+  hipEvent_t* prof_ev[3] = {nullptr, nullptr, nullptr};  // pairs (start, stop)
+  // pass-1 plan knobs
+  int p1_threads = 256;
+  size_t p1_lds_budget = 0;     // 0: the device's opt-in maximum
+  int p1_waves_of_wgs = 1;
+};
+
+namespace {
+
+// timing brackets around one launch sequence of kind k (0 pass 1, 1 pass 2, 2 solve)
+void prof_begin(fct_ctx* c, int k) {
+  if (!c->prof_on || !c->prof_ev[k] || c->prof_n[k] >= fct_ctx::kProfSlots) return;
+  (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k]], c->stream);
+}
+void prof_end(fct_ctx* c, int k) {
+  if (!c->prof_on || !c->prof_ev[k] || c->prof_n[k] >= fct_ctx::kProfSlots) return;
+  (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k] + 1], c->stream);
+  ++c->prof_n[k];
+}
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return FCT_ERR_HIP; \
+  } while (0)
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+size_t esize(fct_dtype dt) { return dt == FCT_F64 ? 8 : (dt == FCT_BF16 ? 2 : 4); }
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(char* b) : base(b) {}
+  template <typename T> T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Size-only pass of a Carve sequence.
+struct Measure {
+  size_t off = 0;
+  template <typename T> void take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    off += count * sizeof(T);
+  }
+};
+
+int ensure_scratch(fct_ctx* c, size_t bytes) {
+  if (bytes <= c->scratch_bytes) return FCT_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->scratch) HIP_TRY(hipFree(c->scratch));
+  c->scratch = nullptr;
+  c->scratch_bytes = 0;
+  size_t want = bytes + bytes / 4 + (1 << 20);
+  if (hipMalloc(&c->scratch, want) != hipSuccess) {
+    c->scratch = nullptr;
+    return FCT_ERR_OOM;
+  }
+  c->scratch_bytes = want;
+  return FCT_OK;
+}
+
+Pass1Plan make_pass1_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, size_t es,
+                          int* err) {
+  Pass1Plan p{};
+  p.threads = c->p1_threads;
+  const int chunk = s > p.threads ? s : p.threads;
+  p.rpt = chunk / p.threads;
+  const size_t tp = (size_t)chunk + chunk / 16;
+  const size_t budget = c->p1_lds_budget ? c->p1_lds_budget : c->lds_optin;
+  const size_t fixed = (size_t)(chunk / 32) * 4 + 256;
+  const size_t per_col = (size_t)r1 * es + tp * es;
+  *err = 0;
+  if (budget <= fixed + per_col) {
+    *err = 1;
+    return p;
+  }
+  int cmax = (int)((budget - fixed) / per_col);
+  if (cmax > q) cmax = q;
+  p.nslices = (q + cmax - 1) / cmax;
+  p.c = (q + p.nslices - 1) / p.nslices;
+  p.nslices = (q + p.c - 1) / p.c;  // every slice non-empty
+  p.lds = (size_t)r1 * p.c * es + (size_t)p.c * tp * es + fixed;
+  int per_cu = (int)((size_t)(160 * 1024) / p.lds);
+  if (per_cu < 1) per_cu = 1;
+  const int64_t target = (int64_t)c->cus * per_cu * c->p1_waves_of_wgs;
+  int64_t nranges = target / p.nslices;
+  if (nranges < 1) nranges = 1;
+  const int64_t min_ranges = (n_pad + 262143) / 262144;  // bound rows summed per partial
+  if (nranges < min_ranges) nranges = min_ranges;
+  const int64_t max_ranges = (n_pad + chunk - 1) / chunk;
+  if (nranges > max_ranges) nranges = max_ranges;
+  int64_t rpr = (n_pad + nranges - 1) / nranges;
+  rpr = (rpr + chunk - 1) / chunk * chunk;
+  p.rows_per_range = rpr;
+  p.nranges = (int)((n_pad + rpr - 1) / rpr);
+  return p;
+}
+
+int check_common(const fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda) {
+  if (!c || !A || n < 1 || d < 1 || lda < n) return FCT_ERR_BAD_ARG;
+  return FCT_OK;
+}
+
+// pinned staging layout: [0, 1024) results, [1024, 2048) counts, [2048, 3072)
+// host-to-device arguments, [3072, 3080) status flags
+constexpr size_t kPinFlags = 3072;
+
+int read_flags(fct_ctx* c) {
+  int h[2] = {0, 0};
+  char* stage = (char*)c->pinned + kPinFlags;
+  HIP_TRY(hipMemcpyAsync(stage, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(h, stage, sizeof(h));
+  HIP_TRY(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->stream));
+  if (h[0]) return FCT_ERR_NONFINITE;
+  if (h[1]) return h[1];
+  return FCT_OK;
+}
+
+// ---- internal steps -------------------------------------------------------
+
+struct SketchBufs {
+  void* partials;
+  double* Yd;
+  double* qrwork;
+};
+
+template <typename C>
+void carve_sketch(C& cv, const Pass1Plan& p, int q, int r1, size_t es, bool want_r) {
+  cv.template take<char>((size_t)p.nranges * q * r1 * es);
+  cv.template take<double>((size_t)r1 * q);
+  if (want_r) cv.template take<double>(qr_work_doubles(r1, q));
+}
+
+int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64_t lda,
+               fct_dtype dt, const void* b, int32_t s, int32_t r1, uint64_t seed, uint32_t flags,
+               void* Y, double* R, double** Yd_out, const Pass1Plan& p) {
+  const int q = d + (b ? 1 : 0);
+  const int64_t n_pad = (n + s - 1) / s * s;
+  const size_t es = esize(dt);
+  void* partials = cv.take<char>((size_t)p.nranges * q * r1 * es);
+  double* Yd = cv.take<double>((size_t)r1 * q);
+  Pass1Args a{};
+  a.A = A;
+  a.b = b;
+  a.lda = lda;
+  a.n = n;
+  a.n_pad = n_pad;
+  a.rows_per_range = p.rows_per_range;
+  a.d = d;
+  a.q = q;
+  a.s = s;
+  a.log2s = ilog2(s);
+  a.r1 = r1;
+  a.c = p.c;
+  a.seed = seed;
+  a.instance = 0;
+  a.sign_flip = (flags & FCT_FLAG_NO_SIGN_FLIP) ? 0 : 1;
+  a.partials = partials;
+  prof_begin(c, 0);
+  HIP_TRY(launch_pass1(a, p, dt == FCT_F64, c->stream));
+  prof_end(c, 0);
+  HIP_TRY(launch_reduce_partials(partials, p.nranges, r1, q, Y, Yd, c->flags + 0, dt == FCT_F64,
+                                 c->stream));
+  if (R) {
+    double* work = cv.take<double>(qr_work_doubles(r1, q));
+    const double rank_tol = dt == FCT_F64 ? 1e-13 : 1e-5;
+    HIP_TRY(launch_qr(Yd, r1, q, work, R, rank_tol, c->flags + 1, c->stream));
+  }
+  if (Yd_out) *Yd_out = Yd;
+  return FCT_OK;
+}
+
+int check_sketch_args(const fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda,
+                      fct_dtype dt, const void* b, int32_t s, int32_t r1, bool want_r) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  const int q = d + (b ? 1 : 0);
+  if (dt != FCT_F32 && dt != FCT_F64) return FCT_ERR_BAD_ARG;
+  if (!is_pow2(s) || s < 2 || s > 4096) return FCT_ERR_BAD_ARG;
+  if (r1 < q || r1 > 65536) return FCT_ERR_BAD_ARG;
+  if (want_r && q > 88) return FCT_ERR_BAD_ARG;
+  return FCT_OK;
+}
+
+struct ProbBufs {
+  double* Md;
+  float* Mf;
+  float* Mfb;
+  uint16_t* Mb;
+  double* wg;
+};
+
+int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, int32_t d,
+              int64_t lda, fct_dtype dt, const double* R, int32_t r2, uint64_t seed,
+              float* lambda, double* sum_lambda) {
+  const int q = d + (xb ? 1 : 0);
+  const int r2p = r2_padded(r2);
+  double* Md = cv.take<double>((size_t)q * r2p);
+  float* Mf = cv.take<float>((size_t)q * r2p);
+  float* Mfb = cv.take<float>((size_t)q * r2p);
+  uint16_t* Mb = cv.take<uint16_t>((size_t)q * r2p);
+  const int kind = dt == FCT_F64 ? kPass2F64 : (dt == FCT_BF16 ? kPass2BF16 : kPass2F32);
+  const int grid = pass2_grid(n, kind);
+  double* wg = cv.take<double>((size_t)grid);
+  HIP_TRY(launch_form_m(R, q, r2, r2p, seed, 0, Md, Mf, Mfb, Mb, c->flags + 1, c->stream));
+  Pass2Args a{};
+  a.A = X;
+  a.b = xb;
+  a.lda = lda;
+  a.n = n;
+  a.d = d;
+  a.q = q;
+  a.r2 = r2;
+  a.M = dt == FCT_F64 ? (const void*)Md : (dt == FCT_BF16 ? (const void*)Mfb : (const void*)Mf);
+  a.Mb = Mb;
+  a.lambda = lambda;
+  a.wg_sums = wg;
+  prof_begin(c, 1);
+  HIP_TRY(launch_pass2(a, kind, c->stream));
+  prof_end(c, 1);
+  HIP_TRY(launch_sum_fixed(wg, grid, sum_lambda, c->stream));
+  return FCT_OK;
+}
+
+template <typename C>
+void carve_probs(C& cv, int q, int r2, int64_t n, int kind) {
+  const int r2p = r2_padded(r2);
+  cv.template take<double>((size_t)q * r2p);
+  cv.template take<float>((size_t)q * r2p);
+  cv.template take<float>((size_t)q * r2p);
+  cv.template take<uint16_t>((size_t)q * r2p);
+  cv.template take<double>((size_t)pass2_grid(n, kind));
+}
+
+int run_select(fct_ctx* c, Carve& cv, const float* lambda, const double* sum_lambda, int64_t n,
+               double s_out, uint64_t seed, int64_t cap, int64_t* idx, double* w, int64_t* S_dev) {
+  const int nb = select_grid(n);
+  SelectArgs a{};
+  a.lambda = lambda;
+  a.sum_lambda = sum_lambda;
+  a.n = n;
+  a.s_out = s_out;
+  a.seed = seed;
+  a.instance = 0;
+  a.p_out = nullptr;
+  a.counts = cv.take<int32_t>((size_t)nb);
+  a.offsets = cv.take<int64_t>((size_t)nb + 1);
+  a.idx = idx;
+  a.w = w;
+  a.cap = cap;
+  a.S = S_dev;
+  HIP_TRY(launch_select(a, c->stream));
+  return FCT_OK;
+}
+
+template <typename C>
+void carve_select(C& cv, int64_t n) {
+  const int nb = select_grid(n);
+  cv.template take<int32_t>((size_t)nb);
+  cv.template take<int64_t>((size_t)nb + 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fct_create(fct_ctx** out, int device, void* hip_stream) {
+  if (!out) return FCT_ERR_BAD_ARG;
+  *out = nullptr;
+  fct_ctx* c = new (std::nothrow) fct_ctx();
+  if (!c) return FCT_ERR_OOM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return FCT_ERR_HIP;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return FCT_ERR_HIP;
+    }
+    c->own_stream = true;
+  }
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
+    c->cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
+      v > 0)
+    c->lds_optin = (size_t)v;
+  else if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+               hipSuccess && v > 0)
+    c->lds_optin = (size_t)v;
+  if (const char* e = std::getenv("FCTL1_P1_THREADS")) c->p1_threads = std::atoi(e);
+  if (const char* e = std::getenv("FCTL1_P1_LDS_BUDGET")) c->p1_lds_budget = (size_t)std::atoll(e);
+  if (const char* e = std::getenv("FCTL1_P1_WAVES")) c->p1_waves_of_wgs = std::atoi(e);
+  if (c->p1_threads != 256 && c->p1_threads != 512 && c->p1_threads != 1024) c->p1_threads = 256;
+  if (c->p1_waves_of_wgs < 1) c->p1_waves_of_wgs = 1;
+  if (hipMalloc(&c->flags, 4 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    fct_destroy(c);
+    return FCT_ERR_OOM;
+  }
+  if (hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream) != hipSuccess) {
+    fct_destroy(c);
+    return FCT_ERR_HIP;
+  }
+  *out = c;
+  return FCT_OK;
+}
+
+void fct_destroy(fct_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < 3; ++k) {
+    if (!c->prof_ev[k]) continue;
+    for (int i = 0; i < 2 * fct_ctx::kProfSlots; ++i) (void)hipEventDestroy(c->prof_ev[k][i]);
+    delete[] c->prof_ev[k];
+  }
+  if (c->scratch) (void)hipFree(c->scratch);
+  if (c->flags) (void)hipFree(c->flags);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* fct_strerror(int status) {
+  switch (status) {
+    case FCT_OK: return "ok";
+    case FCT_ERR_BAD_ARG: return "bad argument";
+    case FCT_ERR_OOM: return "out of device memory";
+    case FCT_ERR_NONFINITE: return "non-finite value in input";
+    case FCT_ERR_RANK_DEFICIENT: return "rank deficient";
+    case FCT_ERR_HIP: return "HIP runtime error";
+    case FCT_ERR_CAPACITY: return "coreset larger than capacity";
+    default: return "unknown status";
+  }
+}
+
+int fct_sync(fct_ctx* c) {
+  if (!c) return FCT_ERR_BAD_ARG;
+  return read_flags(c);
+}
+
+void* fct_stream(fct_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int fct_profile(fct_ctx* c, int enable) {
+  if (!c) return FCT_ERR_BAD_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 3; ++k) {
+    c->prof_n[k] = 0;
+    if (enable && !c->prof_ev[k]) {
+      c->prof_ev[k] = new (std::nothrow) hipEvent_t[2 * fct_ctx::kProfSlots];
+      if (!c->prof_ev[k]) return FCT_ERR_OOM;
+      for (int i = 0; i < 2 * fct_ctx::kProfSlots; ++i)
+        HIP_TRY(hipEventCreateWithFlags(&c->prof_ev[k][i], hipEventDefault));
+    }
+  }
+  c->prof_on = enable != 0;
+  return FCT_OK;
+}
+
+int fct_profile_read(fct_ctx* c, int kind, double* total_ms, int64_t* count) {
+  if (!c || kind < 0 || kind > 2 || !total_ms || !count) return FCT_ERR_BAD_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (int i = 0; i < c->prof_n[kind]; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->prof_ev[kind][2 * i], c->prof_ev[kind][2 * i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = c->prof_n[kind];
+  return FCT_OK;
+}
+
+int fct_sketch(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fct_dtype dt,
+               const void* b, int32_t s, int32_t r1, uint64_t seed, uint32_t flags, void* Y,
+               double* R) {
+  int st = check_sketch_args(c, A, n, d, lda, dt, b, s, r1, R != nullptr);
+  if (st) return st;
+  if (!Y && !R) return FCT_ERR_BAD_ARG;
+  const int q = d + (b ? 1 : 0);
+  const int64_t n_pad = (n + s - 1) / s * s;
+  int perr = 0;
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  Measure m;
+  carve_sketch(m, p, q, r1, esize(dt), R != nullptr);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, R, nullptr, p);
+}
+
+int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+                    fct_dtype dt, const double* R, int32_t r2, uint64_t seed, int64_t s_out,
+                    float* lambda, float* p, double* sum_lambda) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (dt != FCT_F32 && dt != FCT_F64 && dt != FCT_BF16) return FCT_ERR_BAD_ARG;
+  if (!R || r2 < 1 || r2 > 32 || s_out < 1) return FCT_ERR_BAD_ARG;
+  const int q = d + (b ? 1 : 0);
+  const int kind = dt == FCT_F64 ? kPass2F64 : (dt == FCT_BF16 ? kPass2BF16 : kPass2F32);
+  Measure m;
+  if (!lambda) m.take<float>((size_t)n);
+  if (!sum_lambda) m.take<double>(1);
+  carve_probs(m, q, r2, n, kind);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  float* lam = lambda ? lambda : cv.take<float>((size_t)n);
+  double* sl = sum_lambda ? sum_lambda : cv.take<double>(1);
+  if ((st = run_probs(c, cv, A, b, n, d, lda, dt, R, r2, seed, lam, sl))) return st;
+  if (p) {
+    SelectArgs a{};
+    a.lambda = lam;
+    a.sum_lambda = sl;
+    a.n = n;
+    a.s_out = (double)s_out;
+    a.p_out = p;
+    HIP_TRY(launch_probs_only(a, c->stream));
+  }
+  return FCT_OK;
+}
+
+static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d,
+                        int64_t lda, fct_dtype dt, const void* A_lowp, const void* b_lowp,
+                        int64_t ld_lowp, const fct_params* prm, int64_t cap, void* At, void* bt,
+                        double* w, int64_t* idx, int64_t* S_dev, Carve& cv) {
+  const int q = d + 1;
+  const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
+  int perr = 0;
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  double* R = cv.take<double>((size_t)q * q);
+  float* lam = cv.take<float>((size_t)n);
+  double* sl = cv.take<double>(1);
+  int st;
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_sketch(c, sub, A, n, d, lda, dt, b, prm->s, prm->r1, prm->seed, prm->flags,
+                         nullptr, R, nullptr, p)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    const bool lowp = A_lowp != nullptr;
+    if ((st = run_probs(c, sub, lowp ? A_lowp : A, lowp ? b_lowp : b, n, d, lowp ? ld_lowp : lda,
+                        lowp ? FCT_BF16 : dt, R, prm->r2, prm->seed, lam, sl)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_select(c, sub, lam, sl, n, (double)prm->s_out, prm->seed, cap, idx, w, S_dev)))
+      return st;
+  }
+  HIP_TRY(launch_gather(A, b, lda, d, idx, S_dev, cap, At, bt, cap, dt == FCT_F64, c->stream));
+  return FCT_OK;
+}
+
+static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype dt,
+                              const fct_params* prm, bool lowp) {
+  const int q = d + 1;
+  const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
+  int perr = 0;
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), &perr);
+  Measure m;
+  m.take<double>((size_t)q * q);
+  m.take<float>((size_t)n);
+  m.take<double>(1);
+  const size_t base = m.off;
+  Measure a, bb, cc;
+  carve_sketch(a, p, q, prm->r1, esize(dt), true);
+  carve_probs(bb, q, prm->r2, n, lowp ? kPass2BF16 : (dt == FCT_F64 ? kPass2F64 : kPass2F32));
+  carve_select(cc, n);
+  size_t mx = a.off;
+  if (bb.off > mx) mx = bb.off;
+  if (cc.off > mx) mx = cc.off;
+  return base + mx + 1024;
+}
+
+static int check_params(const fct_params* prm, int q) {
+  if (!prm) return FCT_ERR_BAD_ARG;
+  if (!is_pow2(prm->s) || prm->s < 2 || prm->s > 4096) return FCT_ERR_BAD_ARG;
+  if (prm->r1 < q || prm->r1 > 65536 || prm->r2 < 1 || prm->r2 > 32) return FCT_ERR_BAD_ARG;
+  if (q > 65) return FCT_ERR_BAD_ARG;  // solver and panel QR limits: d <= 64
+  return FCT_OK;
+}
+
+int l1_coreset(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+               fct_dtype dt, const void* A_lowp, const void* b_lowp, int64_t ld_lowp,
+               const fct_params* prm, int64_t cap, void* At, void* bt, double* w, int64_t* idx,
+               int64_t* S) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!b || (dt != FCT_F32 && dt != FCT_F64)) return FCT_ERR_BAD_ARG;
+  if ((st = check_params(prm, d + 1))) return st;
+  if (prm->s_out < 1 || cap < 1 || !At || !bt || !w || !idx || !S) return FCT_ERR_BAD_ARG;
+  if (A_lowp && (!b_lowp || ld_lowp < n)) return FCT_ERR_BAD_ARG;
+  const size_t need = coreset_scratch(c, n, d, dt, prm, A_lowp != nullptr) + 256;
+  if ((st = ensure_scratch(c, need))) return st;
+  Carve cv(c->scratch);
+  int64_t* S_dev = cv.take<int64_t>(1);
+  if ((st = coreset_impl(c, A, b, n, d, lda, dt, A_lowp, b_lowp, ld_lowp, prm, cap, At, bt, w,
+                         idx, S_dev, cv)))
+    return st;
+  HIP_TRY(hipMemcpyAsync(c->pinned, S_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  const int fl = read_flags(c);  // synchronizes
+  std::memcpy(S, c->pinned, sizeof(int64_t));
+  if (fl) return fl;
+  if (*S > cap) return FCT_ERR_CAPACITY;
+  return FCT_OK;
+}
+
+int l1_select(fct_ctx* c, const float* lambda, const double* sum_lambda, int64_t n, int64_t s_out,
+              uint64_t seed, int64_t cap, int64_t* idx, double* w, int64_t* S) {
+  if (!c || !lambda || !sum_lambda || n < 1 || s_out < 1 || cap < 1 || !idx || !w || !S)
+    return FCT_ERR_BAD_ARG;
+  Measure m;
+  m.take<int64_t>(1);
+  carve_select(m, n);
+  int st;
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  int64_t* S_dev = cv.take<int64_t>(1);
+  if ((st = run_select(c, cv, lambda, sum_lambda, n, (double)s_out, seed, cap, idx, w, S_dev)))
+    return st;
+  HIP_TRY(hipMemcpyAsync(c->pinned, S_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  const int fl = read_flags(c);
+  std::memcpy(S, c->pinned, sizeof(int64_t));
+  if (fl) return fl;
+  return *S > cap ? FCT_ERR_CAPACITY : FCT_OK;
+}
+
+int l1_solve(fct_ctx* c, const void* At, const void* bt, const double* w, int64_t S, int32_t d,
+             int64_t ldat, fct_dtype dt, int32_t iters, double* x, double* obj) {
+  if (!c || !At || !bt || !w || S < 1 || d < 1 || d > 64 || ldat < S || !x) return FCT_ERR_BAD_ARG;
+  if (dt != FCT_F32 && dt != FCT_F64) return FCT_ERR_BAD_ARG;
+  if (iters <= 0) iters = 60;
+  Measure m;
+  m.take<int64_t>(1);
+  m.take<double>(irls_work_doubles(S, d));
+  m.take<double>(128);
+  int st;
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  int64_t* S_dev = cv.take<int64_t>(1);
+  double* work = cv.take<double>(irls_work_doubles(S, d));
+  double* outv = cv.take<double>(128);
+  std::memcpy((char*)c->pinned + 2048, &S, sizeof(int64_t));
+  HIP_TRY(hipMemcpyAsync(S_dev, (char*)c->pinned + 2048, sizeof(int64_t), hipMemcpyHostToDevice,
+                         c->stream));
+  prof_begin(c, 2);
+  HIP_TRY(launch_irls(At, bt, w, S_dev, S, d, ldat, dt == FCT_F64, iters, work, outv, outv + 64,
+                      c->flags + 1, c->stream));
+  prof_end(c, 2);
+  HIP_TRY(hipMemcpyAsync(c->pinned, outv, 65 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  const int fl = read_flags(c);
+  const double* h = reinterpret_cast<const double*>(c->pinned);
+  for (int i = 0; i < d; ++i) x[i] = h[i];
+  if (obj) *obj = h[64];
+  return fl;
+}
+
+int l1_regress(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+               fct_dtype dt, const void* A_lowp, const void* b_lowp, int64_t ld_lowp, double eps,
+               const fct_params* prm_in, double* x, double* obj, int64_t* S_out) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!b || !x || !prm_in || (dt != FCT_F32 && dt != FCT_F64)) return FCT_ERR_BAD_ARG;
+  fct_params prm = *prm_in;
+  if (prm.s_out <= 0) {
+    if (!(eps > 0.0)) return FCT_ERR_BAD_ARG;
+    prm.s_out = (int64_t)std::ceil(20.0 * (d + 1) / eps);
+  }
+  if ((st = check_params(&prm, d + 1))) return st;
+  if (A_lowp && (!b_lowp || ld_lowp < n)) return FCT_ERR_BAD_ARG;
+  const int iters = prm.irls_iters > 0 ? prm.irls_iters : 60;
+  int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
+  if (cap > n) cap = n;
+  const size_t es = esize(dt);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    Measure m;
+    m.take<int64_t>(1);
+    m.take<char>((size_t)cap * d * es);
+    m.take<char>((size_t)cap * es);
+    m.take<double>((size_t)cap);
+    m.take<int64_t>((size_t)cap);
+    m.take<double>(irls_work_doubles(cap, d));
+    m.take<double>(128);
+    const size_t need = m.off + coreset_scratch(c, n, d, dt, &prm, A_lowp != nullptr) + 256;
+    if ((st = ensure_scratch(c, need))) return st;
+    Carve cv(c->scratch);
+    int64_t* S_dev = cv.take<int64_t>(1);
+    char* At = cv.take<char>((size_t)cap * d * es);
+    char* bt = cv.take<char>((size_t)cap * es);
+    double* w = cv.take<double>((size_t)cap);
+    int64_t* idx = cv.take<int64_t>((size_t)cap);
+    double* work = cv.take<double>(irls_work_doubles(cap, d));
+    double* outv = cv.take<double>(128);
+    Carve rest(c->scratch);
+    rest.off = cv.off;
+    if ((st = coreset_impl(c, A, b, n, d, lda, dt, A_lowp, b_lowp, ld_lowp, &prm, cap, At, bt, w,
+                           idx, S_dev, rest)))
+      return st;
+    prof_begin(c, 2);
+    HIP_TRY(launch_irls(At, bt, w, S_dev, cap, d, cap, dt == FCT_F64, iters, work, outv,
+                        outv + 64, c->flags + 1, c->stream));
+    prof_end(c, 2);
+    HIP_TRY(hipMemcpyAsync(c->pinned, outv, 65 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync((char*)c->pinned + 1024, S_dev, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           c->stream));
+    const int fl = read_flags(c);
+    int64_t S;
+    std::memcpy(&S, (char*)c->pinned + 1024, sizeof(int64_t));
+    if (S_out) *S_out = S;
+    if (fl) return fl;
+    if (S > cap) {
+      cap = S + S / 8 + 1024;
+      continue;
+    }
+    const double* h = reinterpret_cast<const double*>(c->pinned);
+    for (int i = 0; i < d; ++i) x[i] = h[i];
+    if (obj) *obj = h[64];
+    return FCT_OK;
+  }
+  return FCT_ERR_CAPACITY;
+}
+
+int fct_rng_words(fct_ctx* c, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
+                  uint32_t* words) {
+  if (!c || !words || count < 0 || stream > 3) return FCT_ERR_BAD_ARG;
+  if (count == 0) return FCT_OK;
+  HIP_TRY(launch_rng_words(stream, seed, idx0, count, words, c->stream));
+  return FCT_OK;
+}
+
+int fct_pi1_streams(fct_ctx* c, uint64_t seed, int32_t r1, uint64_t j0, int64_t count,
+                    int32_t* bh, float* ch, int32_t* bi, float* ci, int8_t* sg) {
+  if (!c || r1 < 1 || count < 0 || !bh || !ch || !bi || !ci || !sg) return FCT_ERR_BAD_ARG;
+  if (count == 0) return FCT_OK;
+  HIP_TRY(launch_pi1_streams(seed, (uint32_t)r1, j0, count, bh, ch, bi, ci, sg, c->stream));
+  return FCT_OK;
+}
+
+int fct_fwht(fct_ctx* c, float* x, int64_t nblocks, int32_t s) {
+  if (!c || !x || nblocks < 0 || !is_pow2(s) || s < 2 || s > 4096) return FCT_ERR_BAD_ARG;
+  if (nblocks == 0) return FCT_OK;
+  HIP_TRY(launch_fwht(x, nblocks, s, ilog2(s), c->stream));
+  return FCT_OK;
+}
+
+int fct_to_bf16(fct_ctx* c, const float* x, int64_t count, uint16_t* y) {
+  if (!c || !x || !y || count < 0) return FCT_ERR_BAD_ARG;
+  if (count == 0) return FCT_OK;
+  HIP_TRY(launch_to_bf16(x, count, y, c->stream));
+  return FCT_OK;
+}
+
+int fct_l1_objective(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+                     fct_dtype dt, const double* x, double* out) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!b || !x || !out || d > 64 || (dt != FCT_F32 && dt != FCT_F64)) return FCT_ERR_BAD_ARG;
+  const int nparts = 1024;
+  Measure m;
+  m.take<double>(64);
+  m.take<double>(nparts);
+  m.take<double>(1);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  double* xd = cv.take<double>(64);
+  double* parts = cv.take<double>(nparts);
+  double* res = cv.take<double>(1);
+  std::memcpy((char*)c->pinned + 2048, x, d * sizeof(double));
+  HIP_TRY(hipMemcpyAsync(xd, (char*)c->pinned + 2048, d * sizeof(double), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(launch_l1_objective(A, b, lda, n, d, xd, dt == FCT_F64, parts, nparts, res, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->pinned, res, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(out, c->pinned, sizeof(double));
+  return FCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Pass 2: lambda_i = median_j |(X M)_ij| with M = R^-1 Pi2 (regression figure
+// steps 4-5; the proof's running-time paragraph forms R^-1 Pi2 first and then
+// X (R^-1 Pi2), O(n q r2), and takes each median of r2 values in O(r2)).
+//
+// One thread per row: the q values of the row are streamed column by column
+// (coalesced across the wavefront, column-major X), the r2 dot products are
+// accumulated in registers against M held in scalar registers (M is uniform,
+// stored q x R2P with zero padding), the |.| values are sorted by a bitonic
+// network and the median (mean of the two middle values for even r2) is
+// stored.  Each workgroup also emits its FP64 sum of lambda, combined later in
+// a fixed order.
+#include "fct_device.h"
+#include "fct_kernels.h"
+
+namespace fctl1 {
+
+static constexpr int kP2Threads = 256;
+
+template <typename TX> struct Load;
+template <> struct Load<float> {
+  typedef float A;
+  static __device__ __forceinline__ float get(const void* p, int64_t i) {
+    return reinterpret_cast<const float*>(p)[i];
+  }
+};
+template <> struct Load<double> {
+  typedef double A;
+  static __device__ __forceinline__ double get(const void* p, int64_t i) {
+    return reinterpret_cast<const double*>(p)[i];
+  }
+};
+struct Bf16 {};
+template <> struct Load<Bf16> {
+  typedef float A;
+  static __device__ __forceinline__ float get(const void* p, int64_t i) {
+    return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(p)[i] << 16);
+  }
+};
+
+template <typename TA, int N>
+__device__ __forceinline__ void bitonic_sort(TA (&v)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const TA lo = v[i] < v[l] ? v[i] : v[l];
+          const TA hi = v[i] < v[l] ? v[l] : v[i];
+          if ((i & k) == 0) { v[i] = lo; v[l] = hi; }
+          else { v[i] = hi; v[l] = lo; }
+        }
+      }
+    }
+  }
+}
+
+template <typename TA>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+template <typename TX, int R2P>
+__global__ void __launch_bounds__(kP2Threads) pass2_valu_kernel(Pass2Args a) {
+  typedef typename Load<TX>::A TA;
+  __shared__ double red[kP2Threads / 64];
+  const TA* __restrict__ M = reinterpret_cast<const TA*>(a.M);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double lsum = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    TA acc[R2P];
+#pragma unroll
+    for (int j = 0; j < R2P; ++j) acc[j] = TA(0);
+    for (int col = 0; col < a.q; ++col) {
+      TA x = (col < a.d) ? Load<TX>::get(a.A, i + (int64_t)col * a.lda) : -Load<TX>::get(a.b, i);
+#pragma unroll
+      for (int j = 0; j < R2P; ++j) acc[j] = FmaT<TA>::fma(x, M[col * R2P + j], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < R2P; ++j) acc[j] = (j < a.r2) ? fabs(acc[j]) : TA(INFINITY);
+    bitonic_sort<TA, R2P>(acc);
+    const int k1 = (a.r2 - 1) >> 1, k2 = a.r2 >> 1;
+    TA m1 = acc[0], m2 = acc[0];
+#pragma unroll
+    for (int j = 1; j < R2P; ++j) {
+      m1 = (j == k1) ? acc[j] : m1;
+      m2 = (j == k2) ? acc[j] : m2;
+    }
+    const TA lam = TA(0.5) * (m1 + m2);
+    a.lambda[i] = (float)lam;
+    lsum += (double)(float)lam;
+  }
+  const double s = block_sum<TA>(lsum, red);
+  if (threadIdx.x == 0) a.wg_sums[blockIdx.x] = s;
+}
+
+int pass2_grid(int64_t n, int kind) {
+  (void)kind;
+  int64_t want = (n + kP2Threads - 1) / kP2Threads;
+  if (want > 2048) want = 2048;
+  return (int)(want < 1 ? 1 : want);
+}
+
+template <typename TX>
+static hipError_t launch_pass2_t(const Pass2Args& a, int r2p, hipStream_t st) {
+  const int grid = pass2_grid(a.n, 0);
+  switch (r2p) {
+    case 4: hipLaunchKernelGGL((pass2_valu_kernel<TX, 4>), dim3(grid), dim3(kP2Threads), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((pass2_valu_kernel<TX, 8>), dim3(grid), dim3(kP2Threads), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((pass2_valu_kernel<TX, 16>), dim3(grid), dim3(kP2Threads), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((pass2_valu_kernel<TX, 32>), dim3(grid), dim3(kP2Threads), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int r2_padded(int r2) {
+  int p = 4;
+  while (p < r2) p <<= 1;
+  return p;
+}
+
+hipError_t launch_pass2(const Pass2Args& a, int kind, hipStream_t st) {
+  const int r2p = r2_padded(a.r2);
+  if (kind == kPass2F64) return launch_pass2_t<double>(a, r2p, st);
+  if (kind == kPass2BF16) return launch_pass2_t<Bf16>(a, r2p, st);
+  return launch_pass2_t<float>(a, r2p, st);
+}
+
+// out = sum of parts[0..count) in a fixed order (one workgroup).
+__global__ void sum_fixed_kernel(const double* __restrict__ parts, int count, double* out) {
+  __shared__ double red[256 / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) v += parts[i];
+  const double s = block_sum<double>(v, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+hipError_t launch_sum_fixed(const double* parts, int count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_fixed_kernel, dim3(1), dim3(256), 0, st, parts, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace fctl1

@@ -1,0 +1,273 @@
+"""Python binding of libfctl1.so: argument marshalling only.
+
+Every computation runs in the HIP library (include/fctl1.h); this module
+turns torch device tensors into pointers and sizes, calls the C entry point
+of the same name and raises on a non-zero status.  Matrices use the
+library's column-major convention: an n x d matrix A is stored as a torch
+tensor of shape (d, n) (row j is column j).  There is no CPU fallback: the
+module raises ImportError when the built library is absent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so the library binds to the same HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfctl1.so")
+
+FCT_F32, FCT_F64, FCT_BF16 = 0, 1, 2
+FCT_FLAG_NO_SIGN_FLIP = 1
+STATUS = {0: "ok", -1: "bad argument", -2: "out of device memory", -3: "non-finite value in input",
+          -4: "rank deficient", -5: "HIP runtime error", -6: "coreset larger than capacity"}
+
+
+class FctError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class fct_params(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("s_out", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("irls_iters", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_1207_4684_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32, U64, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_double)
+    PD, PI64 = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "fct_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P]),
+        "fct_destroy": (None, [P]),
+        "fct_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "fct_sync": (ctypes.c_int, [P]),
+        "fct_stream": (P, [P]),
+        "fct_sketch": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, P, I32, I32, U64, U32, P, P]),
+        "l1_sample_probs": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64, I64,
+                                           P, P, P]),
+        "l1_coreset": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64,
+                                      ctypes.POINTER(fct_params), I64, P, P, P, P, PI64]),
+        "l1_regress": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64, D,
+                                      ctypes.POINTER(fct_params), PD, PD, PI64]),
+        "fct_rng_words": (ctypes.c_int, [P, U32, U64, U64, I64, P]),
+        "fct_pi1_streams": (ctypes.c_int, [P, U64, I32, U64, I64, P, P, P, P, P]),
+        "fct_fwht": (ctypes.c_int, [P, P, I64, I32]),
+        "fct_to_bf16": (ctypes.c_int, [P, P, I64, P]),
+        "fct_l1_objective": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, PD, PD]),
+        "l1_solve": (ctypes.c_int, [P, P, P, P, I64, I32, I64, ctypes.c_int, I32, PD, PD]),
+        "l1_select": (ctypes.c_int, [P, P, P, I64, I64, U64, I64, P, P, PI64]),
+        "fct_profile": (ctypes.c_int, [P, ctypes.c_int]),
+        "fct_profile_read": (ctypes.c_int, [P, ctypes.c_int, PD, PI64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream", "fct_sketch",
+            "l1_sample_probs", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
+            "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
+            "fct_profile", "fct_profile_read")
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise FctError(st, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dt(t):
+    if t.dtype == torch.float32:
+        return FCT_F32
+    if t.dtype == torch.float64:
+        return FCT_F64
+    if t.dtype in (torch.bfloat16, torch.int16, torch.uint16):
+        return FCT_BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _cm(A):
+    """(d, n) row-major storage of a column-major n x d matrix: returns n, d, lda."""
+    if A.dim() != 2 or (A.stride(1) != 1 and A.shape[1] > 1):
+        raise ValueError("A must be a (d, n) tensor with unit stride along n")
+    # a leading dimension of size 1 may carry any stride
+    return A.shape[1], A.shape[0], (A.stride(0) if A.shape[0] > 1 else A.shape[1])
+
+
+class Context:
+    """fct_create / fct_destroy: binds a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        dev = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.stream = stream
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.fct_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)),
+               "fct_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.fct_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        _check(_lib.fct_sync(self.handle), "fct_sync")
+
+    def profile(self, enable: bool):
+        _check(_lib.fct_profile(self.handle, 1 if enable else 0), "fct_profile")
+
+    def profile_read(self, kind: int):
+        """(total device ms, launches) of kind 0 = pass 1, 1 = pass 2, 2 = solve."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(_lib.fct_profile_read(self.handle, kind, ctypes.byref(ms), ctypes.byref(cnt)),
+               "fct_profile_read")
+        return ms.value, cnt.value
+
+
+def params(s, r1, r2, s_out, seed, flags=0, irls_iters=0):
+    return fct_params(s=s, r1=r1, r2=r2, pad0=0, s_out=int(s_out), seed=seed, flags=flags,
+                      irls_iters=irls_iters)
+
+
+def fct_sketch(ctx, A, b, s, r1, seed, flags=0, want_y=True, want_r=True):
+    """Y = Pi1 X (r1 x q view) and R (q x q view, FP64) of its QR."""
+    n, d, lda = _cm(A)
+    q = d + (1 if b is not None else 0)
+    Y = torch.empty((q, r1), dtype=A.dtype, device=A.device) if want_y else None
+    R = torch.empty((q, q), dtype=torch.float64, device=A.device) if want_r else None
+    _check(_lib.fct_sketch(ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed, flags,
+                           _ptr(Y), _ptr(R)), "fct_sketch")
+    return (Y.t() if Y is not None else None), (R.t() if R is not None else None)
+
+
+def l1_sample_probs(ctx, A, b, R, r2, seed, s_out, want_p=True):
+    """lambda (n, FP32), p (n, FP32) and sum lambda (FP64 device scalar)."""
+    n, d, lda = _cm(A)
+    Rbuf = R.t().contiguous()  # column-major q x q storage of the logical R
+    lam = torch.empty(n, dtype=torch.float32, device=A.device)
+    p = torch.empty(n, dtype=torch.float32, device=A.device) if want_p else None
+    tot = torch.empty(1, dtype=torch.float64, device=A.device)
+    _check(_lib.l1_sample_probs(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf), r2,
+                                seed, int(s_out), _ptr(lam), _ptr(p), _ptr(tot)), "l1_sample_probs")
+    return lam, p, tot
+
+
+def l1_coreset(ctx, A, b, prm, cap, A_lowp=None, b_lowp=None):
+    """(At (S x d view), bt, w, idx, S) of the Bernoulli coreset."""
+    n, d, lda = _cm(A)
+    At = torch.empty((d, cap), dtype=A.dtype, device=A.device)
+    bt = torch.empty(cap, dtype=A.dtype, device=A.device)
+    w = torch.empty(cap, dtype=torch.float64, device=A.device)
+    idx = torch.empty(cap, dtype=torch.int64, device=A.device)
+    S = ctypes.c_int64()
+    ld_lowp = A_lowp.stride(0) if A_lowp is not None else 0
+    st = _lib.l1_coreset(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(A_lowp),
+                         _ptr(b_lowp), ld_lowp, ctypes.byref(prm), cap, _ptr(At), _ptr(bt),
+                         _ptr(w), _ptr(idx), ctypes.byref(S))
+    _check(st, "l1_coreset")
+    k = S.value
+    return At[:, :k].t(), bt[:k], w[:k], idx[:k], k
+
+
+def l1_regress(ctx, A, b, prm, eps=0.05, A_lowp=None, b_lowp=None):
+    """x (numpy FP64), coreset objective, realised coreset size."""
+    import numpy as np
+    n, d, lda = _cm(A)
+    x = (ctypes.c_double * d)()
+    obj = ctypes.c_double()
+    S = ctypes.c_int64()
+    ld_lowp = A_lowp.stride(0) if A_lowp is not None else 0
+    st = _lib.l1_regress(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(A_lowp),
+                         _ptr(b_lowp), ld_lowp, eps, ctypes.byref(prm), x, ctypes.byref(obj),
+                         ctypes.byref(S))
+    _check(st, "l1_regress")
+    return np.array(x[:], dtype=np.float64), obj.value, S.value
+
+
+def l1_select(ctx, lam, sum_lambda, s_out, seed, cap):
+    """idx (ascending), w = 1/p and S of one Bernoulli draw from given lambda."""
+    n = lam.numel()
+    idx = torch.empty(cap, dtype=torch.int64, device=lam.device)
+    w = torch.empty(cap, dtype=torch.float64, device=lam.device)
+    S = ctypes.c_int64()
+    _check(_lib.l1_select(ctx.handle, _ptr(lam), _ptr(sum_lambda), n, int(s_out), seed, cap,
+                          _ptr(idx), _ptr(w), ctypes.byref(S)), "l1_select")
+    return idx[:S.value], w[:S.value], S.value
+
+
+def l1_solve(ctx, At, bt, w, iters=0):
+    """Weighted l1 solve of a device coreset At (d, S storage)."""
+    import numpy as np
+    S, d, ldat = _cm(At)
+    x = (ctypes.c_double * d)()
+    obj = ctypes.c_double()
+    _check(_lib.l1_solve(ctx.handle, _ptr(At), _ptr(bt), _ptr(w), S, d, ldat, _dt(At), iters, x,
+                         ctypes.byref(obj)), "l1_solve")
+    return np.array(x[:], dtype=np.float64), obj.value
+
+
+def fct_rng_words(ctx, stream, seed, idx0, count, device="cuda"):
+    out = torch.empty(4 * count, dtype=torch.int32, device=device)
+    _check(_lib.fct_rng_words(ctx.handle, stream, seed, idx0, count, _ptr(out)), "fct_rng_words")
+    return out
+
+
+def fct_pi1_streams(ctx, seed, r1, j0, count, device="cuda"):
+    bh = torch.empty(count, dtype=torch.int32, device=device)
+    ch = torch.empty(count, dtype=torch.float32, device=device)
+    bi = torch.empty(count, dtype=torch.int32, device=device)
+    ci = torch.empty(count, dtype=torch.float32, device=device)
+    sg = torch.empty(count, dtype=torch.int8, device=device)
+    _check(_lib.fct_pi1_streams(ctx.handle, seed, r1, j0, count, _ptr(bh), _ptr(ch), _ptr(bi),
+                                _ptr(ci), _ptr(sg)), "fct_pi1_streams")
+    return bh, ch, bi, ci, sg
+
+
+def fct_fwht(ctx, x, s):
+    """In-place normalized FWHT of consecutive s-blocks of a float32 device vector."""
+    if x.dtype != torch.float32 or x.numel() % s:
+        raise ValueError("float32 tensor with a multiple of s elements expected")
+    _check(_lib.fct_fwht(ctx.handle, _ptr(x), x.numel() // s, s), "fct_fwht")
+    return x
+
+
+def fct_to_bf16(ctx, x):
+    y = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _check(_lib.fct_to_bf16(ctx.handle, _ptr(x.contiguous()), x.numel(), _ptr(y)), "fct_to_bf16")
+    return y
+
+
+def fct_l1_objective(ctx, A, b, x):
+    n, d, lda = _cm(A)
+    xs = (ctypes.c_double * d)(*[float(v) for v in x])
+    out = ctypes.c_double()
+    _check(_lib.fct_l1_objective(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), xs,
+                                 ctypes.byref(out)), "fct_l1_objective")
+    return out.value

@@ -1,0 +1,58 @@
+"""The C ABI library loads and exports every entry point include/fctl1.h
+declares; argument checks that need no device return FCT_ERR_BAD_ARG (CPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, ensure_built
+
+HEADER = os.path.join(ROOT, "include", "fctl1.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(?:int|void|const char|void)\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text)
+    return sorted(set(n for n in names if n.startswith(("fct_", "l1_"))))
+
+
+def test_header_declares_the_four_paths():
+    names = declared_functions()
+    for n in ("fct_sketch", "l1_sample_probs", "l1_coreset", "l1_regress"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ensure_built())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_bad_arguments_rejected_without_device():
+    lib = ctypes.CDLL(ensure_built())
+    lib.fct_sketch.restype = ctypes.c_int
+    lib.fct_sketch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    assert lib.fct_sketch(None, None, 10, 2, 10, 0, None, 4, 8, 0, 0, None, None) == -1
+    lib.fct_strerror.restype = ctypes.c_char_p
+    assert lib.fct_strerror(-4) == b"rank deficient"
+    assert lib.fct_strerror(0) == b"ok"
+    lib.fct_create.restype = ctypes.c_int
+    lib.fct_create.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    assert lib.fct_create(None, 0, None) == -1
+    lib.fct_sync.argtypes = [ctypes.c_void_p]
+    assert lib.fct_sync(None) == -1
+    lib.fct_destroy.argtypes = [ctypes.c_void_p]
+    lib.fct_destroy(None)
+
+
+def test_binding_names_match_abi():
+    ensure_built()
+    from paper_1207_4684_amd import fctl1
+    assert set(fctl1.EXPORTED) == set(declared_functions())
+    for n in ("fct_sketch", "l1_sample_probs", "l1_coreset", "l1_regress"):
+        assert callable(getattr(fctl1, n))

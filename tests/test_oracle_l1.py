@@ -57,6 +57,20 @@ def test_vertex_certificate():
     assert lower2 <= fl * (1 + 1e-9)
 
 
+def test_dual_lower_bound_valid_and_tight():
+    g = np.random.default_rng(6)
+    A = g.standard_normal((400, 5)) * 10.0 ** g.uniform(-3, 3, 5)
+    A[::97] *= 1e4
+    b = A @ g.standard_normal(5) + g.laplace(size=400) + 1e3 * g.standard_cauchy(400) * (g.random(400) < 0.02)
+    w = g.uniform(0.5, 3.0, 400)
+    xl, fl = l1.lp(A, b, w)
+    lb = l1.dual_lower_bound(A, b, xl, w)
+    assert lb <= fl * (1 + 1e-9) and lb >= fl * (1 - 1e-6)
+    # from a poor candidate the bound stays below the optimum
+    for xc in (np.zeros(5), xl * 1.1, g.standard_normal(5)):
+        assert l1.dual_lower_bound(A, b, xc, w) <= fl * (1 + 1e-9)
+
+
 def test_oracle_path_all_rows_is_exact():
     w = synth.scaled(synth.SMALL, 3000, d=3)
     A, b, _ = synth.generate(w)
