@@ -169,10 +169,12 @@ int l1_select(fct_ctx *ctx, const float *lambda, const double *sum_lambda, int64
 int fct_rng_words(fct_ctx *ctx, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                   uint32_t *words);
 
-/* Per padded row j in [j0, j0 + count): bucket_h, cauchy_h, bucket_i,
- * cauchy_i (stream 0) and sign (stream 1), as the sketch kernels compute
- * them.  Device outputs, each of length count; sign is +1/-1 as int8. */
-int fct_pi1_streams(fct_ctx *ctx, uint64_t seed, int32_t r1, uint64_t j0, int64_t count,
+/* Per padded row j in [j0, j0 + count) of a sketch with block size s:
+ * bucket and Cauchy of its H-half position 2 s floor(j/s) + (j mod s)
+ * (bucket_h, cauchy_h) and of its I-half position (+ s) (bucket_i,
+ * cauchy_i), and its sign (stream 1), as the sketch kernels compute them.
+ * Device outputs, each of length count; sign is +1/-1 as int8. */
+int fct_pi1_streams(fct_ctx *ctx, uint64_t seed, int32_t r1, int32_t s, uint64_t j0, int64_t count,
                     int32_t *bucket_h, float *cauchy_h, int32_t *bucket_i, float *cauchy_i,
                     int8_t *sign);
 

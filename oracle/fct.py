@@ -85,7 +85,7 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
     if sign_flip:
         z *= philox.signs(seed, n_pad, instance)[:, None]
     hz = fwht_blocks(z.reshape(nb, s, q)).reshape(n_pad, q)
-    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, instance)
+    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, s, instance)
     if cauchy_one:
         cH = np.ones_like(cH)
         cI = np.ones_like(cI)
@@ -116,7 +116,7 @@ def pi1_dense(n: int, s: int, r1: int, seed: int, sign_flip: bool = True,
     Ht = np.zeros((2 * n_pad, n_pad))
     for beta in range(nb):
         Ht[2 * s * beta: 2 * s * (beta + 1), s * beta: s * (beta + 1)] = G
-    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, instance)
+    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, s, instance)
     bucket = np.empty(2 * n_pad, dtype=np.int64)
     cauchy = np.empty(2 * n_pad)
     for beta in range(nb):

@@ -18,9 +18,11 @@ Stream layout (a build decision, shared by both sides only through this
 written description): key = (seed mod 2^32, seed >> 32); counter =
 (idx mod 2^32, idx >> 32, stream, instance).
 
-* stream 0, idx = padded input row j: words (w0, w1) give the bucket and the
-  Cauchy of the H-half stacked position of row j, (w2, w3) those of its I-half
-  position.  Bucket = floor(w * r1 / 2^32).
+* stream 0, idx = k >> 1 for stacked position k (the column index of B and C,
+  k < 2 n'): words (w0, w1) give the bucket and the Cauchy of the even
+  position of the pair, (w2, w3) those of the odd one.  Row j of block
+  beta = floor(j / s), t = j mod s, sits at position 2 s beta + t (H-half) and
+  2 s beta + s + t (I-half).  Bucket = floor(w * r1 / 2^32).
 * stream 1, idx = j >> 7: bit (j & 31) of word (j >> 5) & 3 gives the sign
   D(j) = 1 - 2*bit.
 * stream 2, idx = a * r2 + c: word w0 gives the Cauchy Pi2[a, c].
@@ -103,11 +105,28 @@ def cauchy_from_word(w):
     return np.where(neg, -c, c)
 
 
-def pi1_streams(seed: int, n_pad: int, r1: int, instance: int = 0):
+def position_streams(seed: int, k, r1: int, instance: int = 0):
+    """(bucket, Cauchy) of stacked positions k (array) of stream 0."""
+    k = np.asarray(k, dtype=np.uint64)
+    w0, w1, w2, w3 = stream_words(seed, STREAM_PI1, k >> np.uint64(1), instance)
+    odd = (k & np.uint64(1)).astype(bool)
+    return (bucket_from_word(np.where(odd, w2, w0), r1),
+            cauchy_from_word(np.where(odd, w3, w1)))
+
+
+def row_positions(n_pad: int, s: int):
+    """Stacked positions of the H-half and I-half copies of padded rows j < n_pad."""
+    j = np.arange(n_pad, dtype=np.int64)
+    kH = 2 * s * (j // s) + j % s
+    return kH, kH + s
+
+
+def pi1_streams(seed: int, n_pad: int, r1: int, s: int, instance: int = 0):
     """Per padded row j: (bucket_H, cauchy_H, bucket_I, cauchy_I) of stream 0."""
-    w0, w1, w2, w3 = stream_words(seed, STREAM_PI1, np.arange(n_pad, dtype=np.uint64), instance)
-    return (bucket_from_word(w0, r1), cauchy_from_word(w1),
-            bucket_from_word(w2, r1), cauchy_from_word(w3))
+    kH, kI = row_positions(n_pad, s)
+    hH, cH = position_streams(seed, kH, r1, instance)
+    hI, cI = position_streams(seed, kI, r1, instance)
+    return hH, cH, hI, cI
 
 
 def signs(seed: int, n_pad: int, instance: int = 0):

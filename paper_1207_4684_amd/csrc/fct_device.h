@@ -5,9 +5,11 @@
 // with the multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule
 // 0x9E3779B9 / 0xBB67AE85.  Stream layout (key = seed, counter =
 // (idx lo, idx hi, stream, instance)):
-//   stream 0: idx = padded row j -> (bucket_H, cauchy_H, bucket_I, cauchy_I)
-//             of the two stacked positions of row j (FCT1: columns of B and
-//             diagonal of C);
+//   stream 0: idx = k >> 1 for stacked position k (FCT1: column k of B and
+//             diagonal entry k of C): words (0, 1) -> bucket and Cauchy of the
+//             even position, words (2, 3) -> those of the odd one.  Row j of
+//             block b = j / s sits at k = 2 s b + (j mod s) (H-half) and
+//             k + s (I-half);
 //   stream 1: idx = j >> 7, bit j & 31 of word (j >> 5) & 3 -> sign D(j);
 //   stream 2: idx = a * r2 + c, word 0 -> Pi2[a][c];
 //   stream 3: idx = i >> 2, word i & 3 -> uniform deciding row i.
@@ -87,6 +89,20 @@ __device__ __forceinline__ double cauchy_from_word_f64(uint32_t w) {
   const double v = ((double)m + 0.5) * 0x1p-32;
   const double c = 1.0 / tan(3.141592653589793 * v);
   return neg ? -c : c;
+}
+
+// Stacked position of the H-half copy of padded row j (the I-half is + s).
+__device__ __forceinline__ uint64_t h_position(uint64_t j, int log2s) {
+  return ((j >> log2s) << (log2s + 1)) + (j & ((1ull << log2s) - 1));
+}
+
+// (bucket, Cauchy word) of stacked position k (stream 0).
+__device__ __forceinline__ void position_words(uint64_t seed, uint32_t instance, uint64_t k,
+                                               uint32_t r1, uint32_t* bucket, uint32_t* cw) {
+  const uint4 w = stream_words(seed, kStreamPi1, k >> 1, instance);
+  const bool odd = k & 1;
+  *bucket = bucket_from_word(odd ? w.z : w.x, r1);
+  *cw = odd ? w.w : w.y;
 }
 
 // sign D(j) of stream 1 as +1 / -1

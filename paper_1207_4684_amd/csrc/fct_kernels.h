@@ -25,6 +25,8 @@ struct Pass1Args {
 };
 
 struct Pass1Plan {
+  int kind;            // 0: workgroup-tile kernel, 1: wave-level kernel (FP32, s <= 256)
+  bool vec_ok;         // 16-byte aligned columns (wave kernel float4 loads)
   int threads;
   int rpt;             // rows per thread per chunk
   int c;
@@ -35,12 +37,16 @@ struct Pass1Plan {
 };
 
 hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStream_t st);
+size_t pass1_wave_lds(int r1, int c);
+int pass1_wave_rows_quantum();
+hipError_t launch_pass1_wave(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st);
 hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
                                   double* Yd, int* flag, bool f64, hipStream_t st);
 hipError_t launch_rng_words(uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                             uint32_t* out, hipStream_t st);
-hipError_t launch_pi1_streams(uint64_t seed, uint32_t r1, uint64_t j0, int64_t count, int32_t* bh,
-                              float* ch, int32_t* bi, float* ci, int8_t* sg, hipStream_t st);
+hipError_t launch_pi1_streams(uint64_t seed, uint32_t r1, int log2s, uint64_t j0, int64_t count,
+                              int32_t* bh, float* ch, int32_t* bi, float* ci, int8_t* sg,
+                              hipStream_t st);
 hipError_t launch_fwht(float* x, int64_t nblocks, int s, int log2s, hipStream_t st);
 
 // QR of the FP64 sketch (tall r1 x q, column-major, ld = r1) by a tree of

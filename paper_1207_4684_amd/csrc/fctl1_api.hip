@@ -32,6 +32,7 @@ struct fct_ctx {
   int p1_threads = 256;
   size_t p1_lds_budget = 0;     // 0: the device's opt-in maximum
   int p1_waves_of_wgs = 1;
+  int p1_force_tile = 0;        // 1: never use the wave-level pass-1 kernel
 };
 
 namespace {
@@ -97,9 +98,48 @@ int ensure_scratch(fct_ctx* c, size_t bytes) {
   return FCT_OK;
 }
 
+Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int r1, int* err) {
+  Pass1Plan p{};
+  p.kind = 1;
+  p.threads = 512;
+  p.rpt = 1;
+  *err = 0;
+  const size_t budget = c->p1_lds_budget ? c->p1_lds_budget : c->lds_optin;
+  const size_t fixed = pass1_wave_lds(r1, 0) + 16;
+  const size_t per_col = (size_t)r1 * sizeof(double);
+  if (budget <= fixed + per_col) {
+    *err = 1;
+    return p;
+  }
+  int cmax = (int)((budget - fixed) / per_col);
+  if (cmax > q) cmax = q;
+  p.nslices = (q + cmax - 1) / cmax;
+  p.c = (q + p.nslices - 1) / p.nslices;
+  p.nslices = (q + p.c - 1) / p.c;
+  p.lds = pass1_wave_lds(r1, p.c);
+  int per_cu = (int)((size_t)(160 * 1024) / p.lds);
+  if (per_cu < 1) per_cu = 1;
+  const int64_t target = (int64_t)c->cus * per_cu * c->p1_waves_of_wgs;
+  int64_t nranges = target / p.nslices;
+  if (nranges < 1) nranges = 1;
+  const int64_t min_ranges = (n_pad + 262143) / 262144;
+  if (nranges < min_ranges) nranges = min_ranges;
+  const int64_t quantum = pass1_wave_rows_quantum();
+  int64_t rpr = (n_pad + nranges - 1) / nranges;
+  rpr = (rpr + quantum - 1) / quantum * quantum;
+  p.rows_per_range = rpr;
+  p.nranges = (int)((n_pad + rpr - 1) / rpr);
+  return p;
+}
+
 Pass1Plan make_pass1_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, size_t es,
                           int* err) {
+  if (es == sizeof(float) && s <= 256 && !c->p1_force_tile) {
+    Pass1Plan w = make_wave_plan(c, n_pad, q, r1, err);
+    if (!*err) return w;
+  }
   Pass1Plan p{};
+  p.kind = 0;
   p.threads = c->p1_threads;
   const int chunk = s > p.threads ? s : p.threads;
   p.rpt = chunk / p.threads;
@@ -196,7 +236,13 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.sign_flip = (flags & FCT_FLAG_NO_SIGN_FLIP) ? 0 : 1;
   a.partials = partials;
   prof_begin(c, 0);
-  HIP_TRY(launch_pass1(a, p, dt == FCT_F64, c->stream));
+  if (p.kind == 1) {
+    const bool vec_ok = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0) &&
+                        (!b || (((uintptr_t)b & 15) == 0));
+    HIP_TRY(launch_pass1_wave(a, p, vec_ok, c->stream));
+  } else {
+    HIP_TRY(launch_pass1(a, p, dt == FCT_F64, c->stream));
+  }
   prof_end(c, 0);
   HIP_TRY(launch_reduce_partials(partials, p.nranges, r1, q, Y, Yd, c->flags + 0, dt == FCT_F64,
                                  c->stream));
@@ -334,6 +380,7 @@ int fct_create(fct_ctx** out, int device, void* hip_stream) {
   if (const char* e = std::getenv("FCTL1_P1_THREADS")) c->p1_threads = std::atoi(e);
   if (const char* e = std::getenv("FCTL1_P1_LDS_BUDGET")) c->p1_lds_budget = (size_t)std::atoll(e);
   if (const char* e = std::getenv("FCTL1_P1_WAVES")) c->p1_waves_of_wgs = std::atoi(e);
+  if (const char* e = std::getenv("FCTL1_P1_KERNEL")) c->p1_force_tile = std::strcmp(e, "tile") == 0;
   if (c->p1_threads != 256 && c->p1_threads != 512 && c->p1_threads != 1024) c->p1_threads = 256;
   if (c->p1_waves_of_wgs < 1) c->p1_waves_of_wgs = 1;
   if (hipMalloc(&c->flags, 4 * sizeof(int)) != hipSuccess ||
@@ -677,11 +724,13 @@ int fct_rng_words(fct_ctx* c, uint32_t stream, uint64_t seed, uint64_t idx0, int
   return FCT_OK;
 }
 
-int fct_pi1_streams(fct_ctx* c, uint64_t seed, int32_t r1, uint64_t j0, int64_t count,
+int fct_pi1_streams(fct_ctx* c, uint64_t seed, int32_t r1, int32_t s, uint64_t j0, int64_t count,
                     int32_t* bh, float* ch, int32_t* bi, float* ci, int8_t* sg) {
   if (!c || r1 < 1 || count < 0 || !bh || !ch || !bi || !ci || !sg) return FCT_ERR_BAD_ARG;
+  if (!is_pow2(s) || s < 2 || s > 4096) return FCT_ERR_BAD_ARG;
   if (count == 0) return FCT_OK;
-  HIP_TRY(launch_pi1_streams(seed, (uint32_t)r1, j0, count, bh, ch, bi, ci, sg, c->stream));
+  HIP_TRY(launch_pi1_streams(seed, (uint32_t)r1, ilog2(s), j0, count, bh, ch, bi, ci, sg,
+                             c->stream));
   return FCT_OK;
 }
 

@@ -162,14 +162,16 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_solve_kernel(int d, double*
     double eta = work[L.state + 0];
     const double floor_eta = work[L.state + 3];
     work[L.state + 5] = obj;
+    // smoothing floor: eta sum(w) <= 1e-10 of the current objective
+    const double floor_now = 1e-10 * obj / work[L.state + 4];
     if (eta <= 0.0) {
       eta = obj / work[L.state + 4];  // first smoothing level: mean weighted residual
-      work[L.state + 3] = eta * 1e-11;
     } else {
-      const bool at_floor = eta <= floor_eta;
-      if (at_floor && fabs(prev - obj) <= 1e-14 * obj) stop = 1;
-      eta = fmax(floor_eta, 0.5 * eta);
+      const bool at_floor = eta <= floor_eta * 1.0000001;
+      if (at_floor && fabs(prev - obj) <= 1e-11 * obj) stop = 1;
+      eta = fmax(floor_now, 0.5 * eta);
     }
+    work[L.state + 3] = fmax(floor_now, 0.0);
     work[L.state + 1] = obj;
     work[L.state + 0] = eta;
   }
@@ -206,40 +208,50 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_solve_kernel(int d, double*
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    if (bad) {
+  // forward solve L y = rhs (column sweep), then L^T z = y; x = S z
+  for (int k = 0; k < d; ++k) {
+    if (tid == 0) rhs[k] /= G[k * d + k];
+    __syncthreads();
+    for (int i = k + 1 + tid; i < d; i += kIrlsThreads) rhs[i] -= G[i * d + k] * rhs[k];
+    __syncthreads();
+  }
+  for (int k = d - 1; k >= 0; --k) {
+    if (tid == 0) rhs[k] /= G[k * d + k];
+    __syncthreads();
+    for (int i = tid; i < k; i += kIrlsThreads) rhs[i] -= G[k * d + i] * rhs[k];
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) {
       *status = -4;
       work[L.state + 2] = 1.0;
-    } else {
-      double y[kIrlsMaxD];
-      for (int i = 0; i < d; ++i) {
-        double s = rhs[i];
-        for (int k = 0; k < i; ++k) s -= G[i * d + k] * y[k];
-        y[i] = s / G[i * d + i];
-      }
-      for (int i = d - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int k = i + 1; k < d; ++k) s -= G[k * d + i] * y[k];
-        y[i] = s / G[i * d + i];
-      }
-      for (int i = 0; i < d; ++i) work[L.x + i] = y[i] * sc[i];
     }
+  } else {
+    for (int i = tid; i < d; i += kIrlsThreads) work[L.x + i] = rhs[i] * sc[i];
   }
 }
 
-__global__ void irls_init_kernel(int d, const double* __restrict__ w, const int64_t* S_dev,
-                                 int64_t cap, double* work) {
+__global__ void __launch_bounds__(1024) irls_init_kernel(int d, const double* __restrict__ w,
+                                                         const int64_t* S_dev, int64_t cap,
+                                                         double* work) {
   const IrlsLayout L(d);
+  __shared__ double red[16];
+  const int64_t S = min(*S_dev, cap);
+  double sw = 0.0;
+  for (int64_t k = threadIdx.x; k < S; k += blockDim.x) sw += w[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sw += __shfl_xor(sw, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sw;
   if (threadIdx.x < d) work[L.x + threadIdx.x] = 0.0;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const int64_t S = min(*S_dev, cap);
-    double sw = 0.0;
-    for (int64_t k = 0; k < S; ++k) sw += w[k];
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
     work[L.state + 0] = 0.0;
     work[L.state + 1] = 0.0;
     work[L.state + 2] = 0.0;
     work[L.state + 3] = 0.0;
-    work[L.state + 4] = sw > 0.0 ? sw : 1.0;
+    work[L.state + 4] = t > 0.0 ? t : 1.0;
     work[L.state + 5] = 0.0;
   }
 }
@@ -254,7 +266,7 @@ hipError_t launch_irls(const void* At, const void* bt, const double* w, const in
                        int64_t cap, int d, int64_t ldat, bool f64, int iters, double* work,
                        double* x_out, double* obj_out, int* status, hipStream_t st) {
   if (d > kIrlsMaxD || d < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(irls_init_kernel, dim3(1), dim3(128), 0, st, d, w, S_dev, cap, work);
+  hipLaunchKernelGGL(irls_init_kernel, dim3(1), dim3(1024), 0, st, d, w, S_dev, cap, work);
   for (int it = 0; it <= iters; ++it) {
     const int last = it == iters;
     if (f64)

@@ -127,11 +127,14 @@ __global__ void __launch_bounds__(1024) pass1_kernel(Pass1Args a) {
       const int t = threadIdx.x + r * NT;
       const int64_t j = cr + t;
       valid[r] = j < row1;
-      const uint4 w = stream_words(a.seed, kStreamPi1, (uint64_t)j, a.instance);
-      hH[r] = bucket_from_word(w.x, a.r1) * cs;
-      cH[r] = cauchy_t<T>(w.y) * scale_h;
-      hI[r] = bucket_from_word(w.z, a.r1) * cs;
-      cI[r] = cauchy_t<T>(w.w) * scale_i;
+      const uint64_t kH = h_position((uint64_t)j, a.log2s);
+      uint32_t bH, wH, bI, wI;
+      position_words(a.seed, a.instance, kH, a.r1, &bH, &wH);
+      position_words(a.seed, a.instance, kH + a.s, a.r1, &bI, &wI);
+      hH[r] = bH * cs;
+      cH[r] = cauchy_t<T>(wH) * scale_h;
+      hI[r] = bI * cs;
+      cI[r] = cauchy_t<T>(wI) * scale_i;
       float sg = 1.0f;
       if (a.sign_flip) {
         const uint32_t word = sgnw[t >> 5];
@@ -239,16 +242,20 @@ __global__ void rng_words_kernel(uint32_t stream, uint64_t seed, uint64_t idx0, 
   out[4 * i + 3] = w.w;
 }
 
-__global__ void pi1_streams_kernel(uint64_t seed, uint32_t r1, uint64_t j0, int64_t count,
-                                   int32_t* bh, float* ch, int32_t* bi, float* ci, int8_t* sg) {
+__global__ void pi1_streams_kernel(uint64_t seed, uint32_t r1, int log2s, uint64_t j0,
+                                   int64_t count, int32_t* bh, float* ch, int32_t* bi, float* ci,
+                                   int8_t* sg) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const uint64_t j = j0 + (uint64_t)i;
-  const uint4 w = stream_words(seed, kStreamPi1, j, 0);
-  bh[i] = (int32_t)bucket_from_word(w.x, r1);
-  ch[i] = cauchy_from_word(w.y);
-  bi[i] = (int32_t)bucket_from_word(w.z, r1);
-  ci[i] = cauchy_from_word(w.w);
+  const uint64_t kH = h_position(j, log2s);
+  uint32_t b0, w0, b1, w1;
+  position_words(seed, 0, kH, r1, &b0, &w0);
+  position_words(seed, 0, kH + (1ull << log2s), r1, &b1, &w1);
+  bh[i] = (int32_t)b0;
+  ch[i] = cauchy_from_word(w0);
+  bi[i] = (int32_t)b1;
+  ci[i] = cauchy_from_word(w1);
   const uint4 sw = stream_words(seed, kStreamSign, j >> 7, 0);
   sg[i] = (int8_t)sign_from_words(sw, j);
 }
@@ -277,11 +284,12 @@ hipError_t launch_rng_words(uint32_t stream, uint64_t seed, uint64_t idx0, int64
   return hipGetLastError();
 }
 
-hipError_t launch_pi1_streams(uint64_t seed, uint32_t r1, uint64_t j0, int64_t count, int32_t* bh,
-                              float* ch, int32_t* bi, float* ci, int8_t* sg, hipStream_t st) {
+hipError_t launch_pi1_streams(uint64_t seed, uint32_t r1, int log2s, uint64_t j0, int64_t count,
+                              int32_t* bh, float* ch, int32_t* bi, float* ci, int8_t* sg,
+                              hipStream_t st) {
   const int threads = 256;
   hipLaunchKernelGGL(pi1_streams_kernel, dim3((unsigned)((count + threads - 1) / threads)),
-                     dim3(threads), 0, st, seed, r1, j0, count, bh, ch, bi, ci, sg);
+                     dim3(threads), 0, st, seed, r1, log2s, j0, count, bh, ch, bi, ci, sg);
   return hipGetLastError();
 }
 

@@ -1,0 +1,261 @@
+// Pass 1, wave-level form for FP32 data and s <= 256: Y = Pi1 X with
+// Pi1 = 4 B C H~ (section "FCT1 Construction"; n/s Hadamard transforms of
+// size s, a diagonal Cauchy scaling and a hash scatter with 2n non-zeros).
+//
+// A workgroup of 8 waves owns a range of rows and a slice of c columns of
+// X = [A, -b], with a private r1 x c FP64 accumulator in LDS (FP64 LDS atomic
+// adds: on gfx950 they sustain ~9x the rate of FP32 LDS atomic adds, and the
+// sums are FP64).  Each wave takes a
+// contiguous run of 256-row tiles and works on them alone (no workgroup
+// barrier inside the run):
+//   1. one Philox call per pair of stacked positions gives, for the tile's
+//      256 rows, the (bucket, Cauchy) of both copies of every row; 4 rows per
+//      lane, stored to the wave's table in LDS and shared by every column;
+//   2. the slice's columns are processed 4 at a time, 16 lanes per column; a
+//      lane holds 16 rows {4L + i + 64k} of its column (float4 loads, the
+//      next group's loads issued before the current group is processed);
+//   3. the sign D(j) is applied, the I-half copies are added into their
+//      buckets (LDS atomics), the Walsh-Hadamard butterflies over the row
+//      bits held in registers (0, 1, 6, 7) are done in place, one transpose
+//      through LDS brings row bits 2-5 into registers for the remaining
+//      butterflies, and the H-half copies are added into their buckets.
+// Butterflies only run over row bits below log2 s, so a 256-row tile holds
+// 256/s whole blocks.  The accumulator is written once per workgroup; the
+// partials are summed in a fixed order by the reduction kernel.
+#include "fct_device.h"
+#include "fct_kernels.h"
+
+namespace fctl1 {
+
+namespace {
+
+constexpr int kTile = 256;
+constexpr int kWaves = 8;
+constexpr int kTrStride = 272;          // per column group; 16 banks apart
+constexpr int kSignRows = 4096;         // rows covered by one refresh of sign words
+
+struct WaveLds {
+  uint2 entH[kTile];                    // {bucket * c, bits of 4 C / sqrt(s)} of the H-half copy
+  uint2 entI[kTile];                    // {bucket * c, bits of 4 C} of the I-half copy
+  uint32_t sgn[kSignRows / 32];
+  float tr[4 * kTrStride];
+};
+
+__device__ __forceinline__ int trpad(int t) { return t + ((t >> 6) << 2); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void bfly(float& a, float& b) {
+  const float x = a, y = b;
+  a = x + y;
+  b = x - y;
+}
+
+// butterflies along register-index bit `rb` (0..3) of a 16-value vector
+__device__ __forceinline__ void reg_stage(float (&v)[16], int rb) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if (!((r >> rb) & 1)) {
+      switch (rb) {
+        case 0: bfly(v[r], v[r + 1]); break;
+        case 1: bfly(v[r], v[r + 2]); break;
+        case 2: bfly(v[r], v[r + 4]); break;
+        default: bfly(v[r], v[r + 8]); break;
+      }
+    }
+}
+
+__device__ __forceinline__ void load_group(const Pass1Args& a, int c0, int cs, int64_t tile,
+                                           int grp, int g, int L, bool vec_ok, float (&v)[16]) {
+  const int col = grp * 4 + g;
+  if (col >= cs) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = 0.0f;
+    return;
+  }
+  const int gc = c0 + col;
+  const float* p = gc < a.d ? reinterpret_cast<const float*>(a.A) + (int64_t)gc * a.lda
+                            : reinterpret_cast<const float*>(a.b);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t j = tile + 4 * L + 64 * k;
+    if (vec_ok && j + 3 < a.n) {
+      const float4 x = *reinterpret_cast<const float4*>(p + j);
+      v[4 * k + 0] = x.x;
+      v[4 * k + 1] = x.y;
+      v[4 * k + 2] = x.z;
+      v[4 * k + 3] = x.w;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[4 * k + i] = (j + i < a.n) ? p[j + i] : 0.0f;
+    }
+  }
+}
+
+}  // namespace
+
+__device__ __forceinline__ void acc_add(double* p, float v) { atomicAdd(p, (double)v); }
+
+__global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, int vec_ok) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int c0 = blockIdx.y * a.c;
+  const int cs = min(a.c, a.q - c0);
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  const size_t acc_bytes = (((size_t)a.r1 * a.c * sizeof(double)) + 15) & ~size_t(15);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  WaveLds& W = reinterpret_cast<WaveLds*>(smem_raw + acc_bytes)[wave];
+  for (int i = threadIdx.x; i < a.r1 * cs; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+
+  const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_range;
+  const int64_t row1 = min(a.n_pad, row0 + a.rows_per_range);
+  const int64_t sub = a.rows_per_range / kWaves;
+  const int64_t w0 = row0 + wave * sub;
+  const int64_t w1 = min(row1, w0 + sub);
+  const int g = lane >> 4, L = lane & 15;
+  const int ngroups = (cs + 3) >> 2;
+  const float scale_h = 4.0f / sqrtf((float)a.s);
+  const uint64_t s = (uint64_t)a.s;
+  const bool vok = vec_ok != 0;
+
+  float v[16], vn[16];
+  if (w0 < w1) load_group(a, c0, cs, w0, 0, g, L, vok, v);
+  int64_t sign_base = w0;
+
+  for (int64_t tile = w0; tile < w1; tile += kTile) {
+    if (a.sign_flip && ((tile - w0) % kSignRows) == 0) {
+      sign_base = tile;
+      if (lane < kSignRows / 128) {
+        const uint4 sw = stream_words(a.seed, kStreamSign, (uint64_t)(tile >> 7) + lane, a.instance);
+        *reinterpret_cast<uint4*>(&W.sgn[4 * lane]) = sw;
+      }
+    }
+    {
+      // RNG table for rows tile + 4 lane + {0,1,2,3}: positions come in pairs
+      const uint64_t j0 = (uint64_t)tile + 4 * lane;
+      const uint64_t kA = h_position(j0, a.log2s), kB = h_position(j0 + 2, a.log2s);
+      const uint4 wa = stream_words(a.seed, kStreamPi1, kA >> 1, a.instance);
+      const uint4 wb = stream_words(a.seed, kStreamPi1, kB >> 1, a.instance);
+      const uint4 xa = stream_words(a.seed, kStreamPi1, (kA + s) >> 1, a.instance);
+      const uint4 xb = stream_words(a.seed, kStreamPi1, (kB + s) >> 1, a.instance);
+      const uint32_t r1 = (uint32_t)a.r1;
+      const uint32_t ucs = (uint32_t)cs;  // table holds bucket * cs, the cell row offset
+      uint4 h0, h1, i0, i1;
+      h0.x = __umul24(bucket_from_word(wa.x, r1), ucs); h0.y = __float_as_uint(cauchy_from_word(wa.y) * scale_h);
+      h0.z = __umul24(bucket_from_word(wa.z, r1), ucs); h0.w = __float_as_uint(cauchy_from_word(wa.w) * scale_h);
+      h1.x = __umul24(bucket_from_word(wb.x, r1), ucs); h1.y = __float_as_uint(cauchy_from_word(wb.y) * scale_h);
+      h1.z = __umul24(bucket_from_word(wb.z, r1), ucs); h1.w = __float_as_uint(cauchy_from_word(wb.w) * scale_h);
+      i0.x = __umul24(bucket_from_word(xa.x, r1), ucs); i0.y = __float_as_uint(cauchy_from_word(xa.y) * 4.0f);
+      i0.z = __umul24(bucket_from_word(xa.z, r1), ucs); i0.w = __float_as_uint(cauchy_from_word(xa.w) * 4.0f);
+      i1.x = __umul24(bucket_from_word(xb.x, r1), ucs); i1.y = __float_as_uint(cauchy_from_word(xb.y) * 4.0f);
+      i1.z = __umul24(bucket_from_word(xb.z, r1), ucs); i1.w = __float_as_uint(cauchy_from_word(xb.w) * 4.0f);
+      uint4* eh = reinterpret_cast<uint4*>(&W.entH[4 * lane]);
+      uint4* ei = reinterpret_cast<uint4*>(&W.entI[4 * lane]);
+      eh[0] = h0;
+      eh[1] = h1;
+      ei[0] = i0;
+      ei[1] = i1;
+    }
+    wave_sync();
+    const int soff = (int)((tile - sign_base) >> 5);
+
+    for (int grp = 0; grp < ngroups; ++grp) {
+      if (grp + 1 < ngroups) load_group(a, c0, cs, tile, grp + 1, g, L, vok, vn);
+      else if (tile + kTile < w1) load_group(a, c0, cs, tile + kTile, 0, g, L, vok, vn);
+      const int colr = grp * 4 + g;
+      const bool cact = colr < cs;
+      const int col = cact ? colr : cs - 1;  // idle lanes add zeros to a valid cell
+      // sign D(j) (and the minus of the b column) as a sign-bit xor
+      const uint32_t negb = (cact && c0 + col == a.d) ? 0x80000000u : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t bits = 0;
+        if (a.sign_flip) bits = (W.sgn[soff + (L >> 3) + 2 * k] >> ((L & 7) * 4)) & 0xFu;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t m = (((bits >> i) & 1u) << 31) ^ negb;
+          v[4 * k + i] = __uint_as_float(__float_as_uint(v[4 * k + i]) ^ m);
+        }
+      }
+      // I-half copies: rows t = 4 L + i + 64 k
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int t0 = 4 * L + 64 * k;
+        const uint4 e01 = *reinterpret_cast<const uint4*>(&W.entI[t0]);
+        const uint4 e23 = *reinterpret_cast<const uint4*>(&W.entI[t0 + 2]);
+        acc_add(&acc[e01.x + col], __uint_as_float(e01.y) * v[4 * k + 0]);
+        acc_add(&acc[e01.z + col], __uint_as_float(e01.w) * v[4 * k + 1]);
+        acc_add(&acc[e23.x + col], __uint_as_float(e23.y) * v[4 * k + 2]);
+        acc_add(&acc[e23.z + col], __uint_as_float(e23.w) * v[4 * k + 3]);
+      }
+      // butterflies over row bits 0, 1 (register bits 0, 1) and 6, 7 (register bits 2, 3)
+      if (a.log2s > 0) reg_stage(v, 0);
+      if (a.log2s > 1) reg_stage(v, 1);
+      if (a.log2s > 6) reg_stage(v, 2);
+      if (a.log2s > 7) reg_stage(v, 3);
+      // transpose: lane bits (row bits 2-5) <-> register bits
+      if (a.log2s > 2) {
+        float* tr = W.tr + g * kTrStride;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          *reinterpret_cast<float4*>(&tr[trpad(4 * L + 64 * k)]) =
+              make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+        wave_sync();
+        const int base = (L & 3) + 64 * (L >> 2);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = tr[trpad(4 * r + base)];
+        wave_sync();
+        if (a.log2s > 2) reg_stage(v, 0);
+        if (a.log2s > 3) reg_stage(v, 1);
+        if (a.log2s > 4) reg_stage(v, 2);
+        if (a.log2s > 5) reg_stage(v, 3);
+        // H-half copies: rows t = 4 r + (L & 3) + 64 (L >> 2)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const uint2 e = W.entH[4 * r + base];
+          acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[r]);
+        }
+      } else {
+        // s <= 4: rows stay at t = 4 L + i + 64 k
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint2 e = W.entH[4 * L + i + 64 * k];
+            acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[4 * k + i]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = vn[r];
+    }
+    wave_sync();  // table and sign words are rewritten by the next tile
+  }
+  __syncthreads();
+  float* part = reinterpret_cast<float*>(a.partials);
+  for (int col = 0; col < cs; ++col) {
+    float* dst = part + ((size_t)blockIdx.x * a.q + c0 + col) * a.r1;
+    for (int i = threadIdx.x; i < a.r1; i += blockDim.x) dst[i] = (float)acc[i * cs + col];
+  }
+}
+
+size_t pass1_wave_lds(int r1, int c) {
+  return ((((size_t)r1 * c * sizeof(double)) + 15) & ~size_t(15)) + kWaves * sizeof(WaveLds);
+}
+
+int pass1_wave_rows_quantum() { return kWaves * kTile; }
+
+hipError_t launch_pass1_wave(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)pass1_wave_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pass1_wave_kernel, dim3(p.nranges, p.nslices), dim3(kWaves * 64), p.lds, st,
+                     a, vec_ok ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace fctl1

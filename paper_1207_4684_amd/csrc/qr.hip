@@ -14,7 +14,7 @@
 
 namespace fctl1 {
 
-static constexpr int kQrThreads = 256;
+static constexpr int kQrThreads = 1024;
 static constexpr int kQrLdsDoubles = 16000;  // 125 KB panel budget
 
 static int qr_panel_rows(int q) { return kQrLdsDoubles / q; }
@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(const double* __re
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Pm = reinterpret_cast<double*>(smem_raw);
   __shared__ double red[kQrThreads / 64];
+  __shared__ double wdot[128];
   __shared__ double sh_beta, sh_rkk;
   const int p = blockIdx.x;
   const int64_t r0 = (int64_t)p * P;
@@ -70,12 +71,20 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(const double* __re
     __syncthreads();
     const double beta = sh_beta;
     if (beta != 0.0) {
+      // w_j = beta * v^T P[:, j] for the trailing columns (one wave per column)
       for (int j = k + 1 + wave; j < q; j += nw) {
-        double* colj = Pm + (size_t)j * m;
+        const double* colj = Pm + (size_t)j * m;
         double dot = 0.0;
         for (int i = k + lane; i < m; i += 64) dot += colk[i] * colj[i];
-        dot = wave_sum(dot) * beta;
-        for (int i = k + lane; i < m; i += 64) colj[i] -= dot * colk[i];
+        dot = wave_sum(dot);
+        if (lane == 0) wdot[j] = dot * beta;
+      }
+      __syncthreads();
+      // P[i, j] -= v_i w_j over all trailing (i, j) pairs
+      const int rows = m - k, cols = q - k - 1;
+      for (int e = tid; e < rows * cols; e += kQrThreads) {
+        const int i = k + e % rows, j = k + 1 + e / rows;
+        Pm[i + (size_t)j * m] -= colk[i] * wdot[j];
       }
     }
     __syncthreads();

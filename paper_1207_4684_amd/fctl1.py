@@ -57,7 +57,7 @@ def _load():
         "l1_regress": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64, D,
                                       ctypes.POINTER(fct_params), PD, PD, PI64]),
         "fct_rng_words": (ctypes.c_int, [P, U32, U64, U64, I64, P]),
-        "fct_pi1_streams": (ctypes.c_int, [P, U64, I32, U64, I64, P, P, P, P, P]),
+        "fct_pi1_streams": (ctypes.c_int, [P, U64, I32, I32, U64, I64, P, P, P, P, P]),
         "fct_fwht": (ctypes.c_int, [P, P, I64, I32]),
         "fct_to_bf16": (ctypes.c_int, [P, P, I64, P]),
         "fct_l1_objective": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, PD, PD]),
@@ -239,13 +239,13 @@ def fct_rng_words(ctx, stream, seed, idx0, count, device="cuda"):
     return out
 
 
-def fct_pi1_streams(ctx, seed, r1, j0, count, device="cuda"):
+def fct_pi1_streams(ctx, seed, r1, s, j0, count, device="cuda"):
     bh = torch.empty(count, dtype=torch.int32, device=device)
     ch = torch.empty(count, dtype=torch.float32, device=device)
     bi = torch.empty(count, dtype=torch.int32, device=device)
     ci = torch.empty(count, dtype=torch.float32, device=device)
     sg = torch.empty(count, dtype=torch.int8, device=device)
-    _check(_lib.fct_pi1_streams(ctx.handle, seed, r1, j0, count, _ptr(bh), _ptr(ch), _ptr(bi),
+    _check(_lib.fct_pi1_streams(ctx.handle, seed, r1, s, j0, count, _ptr(bh), _ptr(ch), _ptr(bi),
                                 _ptr(ci), _ptr(sg)), "fct_pi1_streams")
     return bh, ch, bi, ci, sg
 

@@ -53,35 +53,37 @@ def test_rng_words_bit_exact(F, ctx, stream):
         assert np.array_equal(got, ref)
 
 
-def test_pi1_streams_buckets_signs_exact_cauchy_8ulp(F, ctx):
+@pytest.mark.parametrize("s", [2, 256, 4096])
+def test_pi1_streams_buckets_signs_exact_cauchy_8ulp(F, ctx, s):
     seed, r1 = 77, 2048
     for j0 in (0, 2**33 + 128):
         n = 1 << 16
-        bh, ch, bi, ci, sg = (host(t) for t in F.fct_pi1_streams(ctx, seed, r1, j0, n))
-        w = philox.stream_words(seed, 0, np.arange(j0, j0 + n, dtype=np.uint64))
-        assert np.array_equal(bh, philox.bucket_from_word(w[0], r1))
-        assert np.array_equal(bi, philox.bucket_from_word(w[2], r1))
-        for got, word in ((ch, w[1]), (ci, w[3])):
-            ref = philox.cauchy_from_word(word)
+        bh, ch, bi, ci, sg = (host(t) for t in F.fct_pi1_streams(ctx, seed, r1, s, j0, n))
+        j = np.arange(j0, j0 + n, dtype=np.int64)
+        kH = 2 * s * (j // s) + j % s
+        rbh, rch = philox.position_streams(seed, kH, r1)
+        rbi, rci = philox.position_streams(seed, kH + s, r1)
+        assert np.array_equal(bh, rbh) and np.array_equal(bi, rbi)
+        for got, ref in ((ch, rch), (ci, rci)):
             ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
             assert np.max(np.abs(got.astype(np.float64) - ref) / ulp) <= 8.0
         ncall = (j0 + n + 127) // 128 - j0 // 128
         sw = np.stack(philox.stream_words(seed, 1, np.arange(j0 // 128, j0 // 128 + ncall, dtype=np.uint64)), 1).reshape(-1)
-        j = np.arange(j0, j0 + n, dtype=np.uint64)
-        word = sw[((j >> np.uint64(5)) - np.uint64(4 * (j0 // 128))).astype(np.int64)].astype(np.uint64)
-        ref_sg = 1 - 2 * ((word >> (j & np.uint64(31))) & np.uint64(1)).astype(np.int64)
+        ju = j.astype(np.uint64)
+        word = sw[((ju >> np.uint64(5)) - np.uint64(4 * (j0 // 128))).astype(np.int64)].astype(np.uint64)
+        ref_sg = 1 - 2 * ((word >> (ju & np.uint64(31))) & np.uint64(1)).astype(np.int64)
         assert np.array_equal(sg.astype(np.int64), ref_sg)
 
 
-def test_cauchy_edge_words(F, ctx):
-    # words that reach the poles and the centre: scan all calls whose w1 is extreme is
-    # impractical, so check the conversion through stream 0 on a wide range and
-    # compare the extreme magnitudes seen
-    bh, ch, bi, ci, sg = (host(t) for t in F.fct_pi1_streams(ctx, 5, 16, 0, 1 << 20))
-    w = philox.stream_words(5, 0, np.arange(1 << 20, dtype=np.uint64))
-    ref = philox.cauchy_from_word(w[1])
+def test_cauchy_extreme_words(F, ctx):
+    # the largest |C| among 2^21 draws (a word near the poles) keeps its sign and value
+    bh, ch, bi, ci, sg = (host(t) for t in F.fct_pi1_streams(ctx, 5, 16, 2, 0, 1 << 20))
+    _, ref = philox.position_streams(5, np.arange(2 << 20), 16)
+    got = np.empty(2 << 20)
+    got[0::4], got[1::4] = ch[0::2], ch[1::2]
+    got[2::4], got[3::4] = ci[0::2], ci[1::2]
     i = np.argmax(np.abs(ref))
-    assert np.sign(ch[i]) == np.sign(ref[i]) and abs(ch[i] / ref[i] - 1) < 1e-6
+    assert np.sign(got[i]) == np.sign(ref[i]) and abs(got[i] / ref[i] - 1) < 1e-6
 
 
 # ---- FWHT ------------------------------------------------------------------

@@ -56,7 +56,7 @@ def test_dense_pi1_has_paper_structure():
     # sum of Cauchy-weighted basis vectors: B has exactly one 1 per column.
     n, s, r1 = 8, 4, 5
     P = fct.pi1_dense(n, s, r1, seed=1, sign_flip=False)
-    hH, cH, hI, cI = philox.pi1_streams(1, n, r1)
+    hH, cH, hI, cI = philox.pi1_streams(1, n, r1, s)
     # column 0 of block 0: H-half rows contribute cH[t] * H[t, 0] = cH[t]/sqrt(s) into hH[t],
     # and the I-half contributes cI[0] into hI[0].
     col = np.zeros(r1)

@@ -56,7 +56,7 @@ def test_philox_matches_rocrand_host_engine(tmp_path_factory):
 
 def test_buckets_uniform_chi2():
     r1 = 97
-    h = philox.pi1_streams(11, 1 << 16, r1)[0]
+    h = philox.pi1_streams(11, 1 << 16, r1, 256)[0]
     assert h.min() >= 0 and h.max() < r1
     counts = np.bincount(h, minlength=r1)
     chi2, pval = scipy.stats.chisquare(counts)
@@ -105,6 +105,18 @@ def test_signs_and_sampling_words_balanced():
     assert scipy.stats.kstest(u, "uniform").pvalue > 1e-4
     # an offset window agrees with the full stream
     assert np.array_equal(philox.sample_words(9, 37, start=101), philox.sample_words(9, 200)[101:138])
+
+
+def test_position_pairs_share_a_call():
+    # positions 2c and 2c+1 use words (w0, w1) and (w2, w3) of call c
+    w = philox.stream_words(4, 0, np.arange(10))
+    h, c = philox.position_streams(4, np.arange(20), 64)
+    assert np.array_equal(h[0::2], philox.bucket_from_word(w[0], 64))
+    assert np.array_equal(h[1::2], philox.bucket_from_word(w[2], 64))
+    assert np.array_equal(c[1::2], philox.cauchy_from_word(w[3]))
+    kH, kI = philox.row_positions(12, 4)
+    assert list(kH) == [0, 1, 2, 3, 8, 9, 10, 11, 16, 17, 18, 19]
+    assert list(kI) == [4, 5, 6, 7, 12, 13, 14, 15, 20, 21, 22, 23]
 
 
 def test_streams_and_instances_independent():
