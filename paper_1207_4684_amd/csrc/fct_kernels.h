@@ -112,9 +112,12 @@ hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, c
 
 // Step 8: weighted l1 solve by FP64 IRLS.
 size_t irls_work_doubles(int64_t S, int d);
+// Persistent cooperative IRLS: S_hint (host) sizes the grid, the device count
+// S_dev (clamped to cap) is the number of rows; x_out[d], obj_out[1].
 hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,
-                       int64_t cap, int d, int64_t ldat, bool f64, int iters, double* work,
-                       double* x_out, double* obj_out, int* status, hipStream_t st);
+                       int64_t cap, int64_t S_hint, int d, int64_t ldat, bool f64, int iters,
+                       double* work, double* x_out, double* obj_out, int* status,
+                       hipStream_t st);
 
 hipError_t launch_to_bf16(const float* x, int64_t count, uint16_t* y, hipStream_t st);
 hipError_t launch_l1_objective(const void* A, const void* b, int64_t lda, int64_t n, int d,

@@ -625,7 +625,7 @@ int l1_solve(fct_ctx* c, const void* At, const void* bt, const double* w, int64_
              int64_t ldat, fct_dtype dt, int32_t iters, double* x, double* obj) {
   if (!c || !At || !bt || !w || S < 1 || d < 1 || d > 64 || ldat < S || !x) return FCT_ERR_BAD_ARG;
   if (dt != FCT_F32 && dt != FCT_F64) return FCT_ERR_BAD_ARG;
-  if (iters <= 0) iters = 60;
+  if (iters <= 0) iters = 80;
   Measure m;
   m.take<int64_t>(1);
   m.take<double>(irls_work_doubles(S, d));
@@ -640,8 +640,8 @@ int l1_solve(fct_ctx* c, const void* At, const void* bt, const double* w, int64_
   HIP_TRY(hipMemcpyAsync(S_dev, (char*)c->pinned + 2048, sizeof(int64_t), hipMemcpyHostToDevice,
                          c->stream));
   prof_begin(c, 2);
-  HIP_TRY(launch_irls(At, bt, w, S_dev, S, d, ldat, dt == FCT_F64, iters, work, outv, outv + 64,
-                      c->flags + 1, c->stream));
+  HIP_TRY(launch_irls(At, bt, w, S_dev, S, S, d, ldat, dt == FCT_F64, iters, work, outv,
+                      outv + 64, c->flags + 1, c->stream));
   prof_end(c, 2);
   HIP_TRY(hipMemcpyAsync(c->pinned, outv, 65 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   const int fl = read_flags(c);
@@ -664,7 +664,7 @@ int l1_regress(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, i
   }
   if ((st = check_params(&prm, d + 1))) return st;
   if (A_lowp && (!b_lowp || ld_lowp < n)) return FCT_ERR_BAD_ARG;
-  const int iters = prm.irls_iters > 0 ? prm.irls_iters : 60;
+  const int iters = prm.irls_iters > 0 ? prm.irls_iters : 80;
   int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
   if (cap > n) cap = n;
   const size_t es = esize(dt);
@@ -693,7 +693,8 @@ int l1_regress(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, i
                            idx, S_dev, rest)))
       return st;
     prof_begin(c, 2);
-    HIP_TRY(launch_irls(At, bt, w, S_dev, cap, d, cap, dt == FCT_F64, iters, work, outv,
+    const int64_t S_hint = prm.s_out < cap ? prm.s_out : cap;
+    HIP_TRY(launch_irls(At, bt, w, S_dev, cap, S_hint, d, cap, dt == FCT_F64, iters, work, outv,
                         outv + 64, c->flags + 1, c->stream));
     prof_end(c, 2);
     HIP_TRY(hipMemcpyAsync(c->pinned, outv, 65 * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -4,282 +4,546 @@
 // iteratively reweighted least squares on the smoothed objective
 // sum_k w_k sqrt(r_k^2 + eta^2) (each step minimizes the quadratic majorant
 // sum_k w_k r_k^2 / sqrt(r_k^2 + eta^2), so the smoothed objective never
-// increases), with eta decreased geometrically to a floor; the smoothed and
-// the exact objective differ by at most eta sum_k w_k.
+// increases), with eta shrunk geometrically to a floor; the smoothed and the
+// exact objective differ by at most eta sum_k w_k.
 //
-// Each iteration is two kernels: many workgroups accumulate partial weighted
-// Gram matrices A^T W A and right-hand sides A^T W b (and the objective at the
-// current x); one workgroup sums the partials in a fixed order and solves the
-// normal equations by Cholesky.  A device flag ends the iteration early once
-// the objective has stopped moving at the smallest eta.
+// The whole iteration is one persistent cooperative kernel.  Each workgroup
+// owns a contiguous range of coreset rows and, per iteration, accumulates the
+// weighted Gram matrix of [A b] over its rows in 4x4 register blocks (FP64),
+// writes it as a partial, and meets the others at a grid barrier.  Every
+// workgroup then sums all partials in the same fixed order and runs the same
+// Cholesky solve, so all of them hold bit-identical x, objective and stopping
+// decision without a second barrier.  Partials are double-buffered by
+// iteration parity: a workgroup can run at most one iteration ahead.
 #include "fct_device.h"
 #include "fct_kernels.h"
 
+#include <cstdlib>
+
 namespace fctl1 {
 
-static constexpr int kIrlsWgs = 64;
 static constexpr int kIrlsThreads = 256;
-static constexpr int kIrlsTile = 64;
 static constexpr int kIrlsMaxD = 64;
-static constexpr int kIrlsPer = (kIrlsMaxD * (kIrlsMaxD + 1) / 2 + kIrlsMaxD + kIrlsThreads - 1) / kIrlsThreads;
+static constexpr int kIrlsMaxWgs = 64;
+static constexpr int kIrlsRowTarget = 320;  // coreset rows per workgroup the grid is sized for
+static constexpr size_t kIrlsLdsBytes = 150 * 1024;
+static constexpr int kGjMax = (64 * 65 + 255) / 256;  // augmented entries per thread, d = 64
+static constexpr unsigned kSpinLimit = 1u << 24;  // polls of ~64 clocks each before giving up
 
-// work layout (doubles)
-struct IrlsLayout {
-  int d;
-  size_t x, part, obj, state, total;
-  __host__ __device__ IrlsLayout(int d_) : d(d_) {
-    const size_t E = (size_t)d * d + d;
-    x = 0;
-    part = x + ((d + 7) & ~7);
-    obj = part + (size_t)kIrlsWgs * E;
-    state = obj + kIrlsWgs;
-    total = state + 8;
+// Geometry of the augmented Gram [A b]^T W [A b] in 4x4 blocks, and the LDS
+// plan: resident rows (element type T) + one weight per row, then the Gram
+// area (also the per-group partial sums before the barrier) and vectors.
+struct IrlsGeom {
+  int d, q, NB, W, nbp, groups, pstride, E;
+  size_t gdoubles, fixed_bytes;
+  __host__ __device__ IrlsGeom(int d_, size_t elem) {
+    d = d_;
+    q = d + 1;
+    NB = (q + 3) / 4;
+    W = 4 * NB;
+    nbp = NB * (NB + 1) / 2;
+    groups = kIrlsThreads / nbp;
+    if (groups < 1) groups = 1;
+    E = nbp * 16 + 1;
+    pstride = (E + 7) & ~7;
+    const size_t g1 = (size_t)d * d, g2 = (size_t)groups * nbp * 16;
+    gdoubles = ((g1 > g2 ? g1 : g2) + 1) & ~(size_t)1;  // keeps the vectors 16-byte aligned
+    fixed_bytes = (((gdoubles + 64 + 72 + 80 + 16 + 256 + 264 + 264 + 64 + 256) * sizeof(double)) + 15) &
+                  ~(size_t)15;
+    row_bytes = (size_t)W * elem + sizeof(double);
+    rmax = (int)((kIrlsLdsBytes - fixed_bytes) / row_bytes);
+    rmax &= ~63;
   }
+  size_t row_bytes;
+  int rmax;  // rows a workgroup holds in LDS at once
+  __host__ __device__ size_t lds_bytes() const { return fixed_bytes + (size_t)rmax * row_bytes; }
 };
-// state: [0] eta (<= 0: plain weighted least squares), [1] previous objective,
-//        [2] done flag, [3] eta floor, [4] sum of weights, [5] last objective
+
+struct IrlsArgs {
+  const void* At;
+  const void* bt;
+  const double* w;
+  const int64_t* S_dev;
+  int64_t cap;
+  int64_t ldat;
+  int d;
+  int iters;
+  double* part;   // 2 x gridDim.x x pstride
+  unsigned* bar;  // [0] arrival counter (zero at launch), [1] abort flag
+  double* x_out;
+  double* obj_out;
+  int* status;
+};
 
 size_t irls_work_doubles(int64_t S, int d) {
   (void)S;
-  return IrlsLayout(d).total;
+  const IrlsGeom g(d, sizeof(double));
+  return 2 * (size_t)kIrlsMaxWgs * g.pstride + 8;
+}
+
+// Grid-wide barrier on a monotone arrival counter.  The agent-scope fences
+// publish this workgroup's partial stores before its arrival and make the
+// others' visible after the wait.  The wait is bounded: on timeout the abort
+// flag is raised so every workgroup leaves at its next barrier.
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int* ok_sh) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          ++spins > kSpinLimit) {
+        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return *ok_sh != 0;
+}
+
+__device__ inline void block_pair(int pr, int NB, int& bi, int& bj) {
+  int i = 0, rem = pr;
+  while (rem >= NB - i) {
+    rem -= NB - i;
+    ++i;
+  }
+  bi = i;
+  bj = i + rem;
+}
+
+__device__ inline double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
+__device__ inline double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kIrlsThreads) irls_gram_kernel(
-    const T* __restrict__ At, const T* __restrict__ bt, const double* __restrict__ w,
-    const int64_t* __restrict__ S_dev, int64_t cap, int d, int64_t ldat, double* work) {
-  const IrlsLayout L(d);
-  if (work[L.state + 2] != 0.0) return;
-  __shared__ double xs[kIrlsMaxD];
-  __shared__ double tile[kIrlsTile * (kIrlsMaxD + 1)];
-  __shared__ double om[kIrlsTile];
-  __shared__ double red[kIrlsThreads / 64];
-  const int tid = threadIdx.x;
-  const int64_t S = min(*S_dev, cap);
-  const double eta = work[L.state + 0];
-  for (int k = tid; k < d; k += kIrlsThreads) xs[k] = work[L.x + k];
-  const int E = d * (d + 1) / 2 + d;
-  // entries this thread owns: upper-triangle (i <= j) pairs, then rhs k
-  double accv[kIrlsPer];
-  int ei[kIrlsPer], ej[kIrlsPer];
-#pragma unroll
-  for (int u = 0; u < kIrlsPer; ++u) {
-    accv[u] = 0.0;
-    const int e = tid + u * kIrlsThreads;
-    int i = 0, j = 0;
-    if (e < d * (d + 1) / 2) {
-      int rem = e;
-      while (rem >= d - i) { rem -= d - i; ++i; }
-      j = i + rem;
-    } else if (e < E) {
-      i = e - d * (d + 1) / 2;
-      j = d;  // right-hand side entry: sum om a_i b
-    }
-    ei[u] = i;
-    ej[u] = j;
-  }
-  double objp = 0.0;
-  const int64_t per = (S + kIrlsWgs - 1) / kIrlsWgs;
-  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(S, lo + per);
-  for (int64_t t0 = lo; t0 < hi; t0 += kIrlsTile) {
-    const int nt = (int)min<int64_t>(kIrlsTile, hi - t0);
-    __syncthreads();
-    for (int e = tid; e < nt * (d + 1); e += kIrlsThreads) {
-      const int rr = e % nt, c = e / nt;
-      const double v = c < d ? (double)At[t0 + rr + (int64_t)c * ldat] : (double)bt[t0 + rr];
-      tile[rr * (kIrlsMaxD + 1) + c] = v;
-    }
-    __syncthreads();
-    if (tid < nt) {
-      const double* row = tile + tid * (kIrlsMaxD + 1);
-      double r = -row[d];
-      for (int c = 0; c < d; ++c) r = fma(row[c], xs[c], r);
-      const double wk = w[t0 + tid];
-      objp += wk * fabs(r);
-      om[tid] = eta > 0.0 ? wk / sqrt(r * r + eta * eta) : wk;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kIrlsPer; ++u) {
-      if (tid + u * kIrlsThreads < E) {
-        const int i = ei[u], j = ej[u];
-        double s = 0.0;
-        for (int rr = 0; rr < nt; ++rr) {
-          const double* row = tile + rr * (kIrlsMaxD + 1);
-          s = fma(om[rr] * row[i], row[j], s);
-        }
-        accv[u] += s;
-      }
-    }
-  }
-  double* part = work + L.part + (size_t)blockIdx.x * ((size_t)d * d + d);
-#pragma unroll
-  for (int u = 0; u < kIrlsPer; ++u)
-    if (tid + u * kIrlsThreads < E) part[tid + u * kIrlsThreads] = accv[u];
-  // objective partial
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) objp += __shfl_xor(objp, o, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = objp;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int k = 0; k < kIrlsThreads / 64; ++k) s += red[k];
-    work[L.obj + blockIdx.x] = s;
-  }
+__device__ inline void load4(const T* p, double (&v)[4]);
+template <>
+__device__ inline void load4<float>(const float* p, double (&v)[4]) {
+  const float4 f = *reinterpret_cast<const float4*>(p);
+  v[0] = f.x;
+  v[1] = f.y;
+  v[2] = f.z;
+  v[3] = f.w;
+}
+template <>
+__device__ inline void load4<double>(const double* p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
 }
 
-__global__ void __launch_bounds__(kIrlsThreads) irls_solve_kernel(int d, double* work, int last,
-                                                                  int* status) {
-  const IrlsLayout L(d);
-  if (work[L.state + 2] != 0.0) return;
-  __shared__ double G[kIrlsMaxD * kIrlsMaxD];
-  __shared__ double rhs[kIrlsMaxD];
-  __shared__ double piv;
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  const int E = d * (d + 1) / 2 + d;
-  for (int e = tid; e < E; e += kIrlsThreads) {
-    double s = 0.0;
-    for (int g = 0; g < kIrlsWgs; ++g) s += work[L.part + (size_t)g * ((size_t)d * d + d) + e];
-    if (e < d * (d + 1) / 2) {
-      int i = 0, rem = e;
-      while (rem >= d - i) { rem -= d - i; ++i; }
-      const int j = i + rem;
-      G[i * d + j] = s;
-      G[j * d + i] = s;
-    } else {
-      rhs[e - d * (d + 1) / 2] = s;
-    }
-  }
-  if (tid == 0) bad = 0;
-  __shared__ int stop;
-  // objective at the x used by the Gram pass
-  if (tid == 0) {
-    stop = 0;
-    double obj = 0.0;
-    for (int g = 0; g < kIrlsWgs; ++g) obj += work[L.obj + g];
-    const double prev = work[L.state + 1];
-    double eta = work[L.state + 0];
-    const double floor_eta = work[L.state + 3];
-    work[L.state + 5] = obj;
-    // smoothing floor: eta sum(w) <= 1e-10 of the current objective
-    const double floor_now = 1e-10 * obj / work[L.state + 4];
-    if (eta <= 0.0) {
-      eta = obj / work[L.state + 4];  // first smoothing level: mean weighted residual
-    } else {
-      const bool at_floor = eta <= floor_eta * 1.0000001;
-      if (at_floor && fabs(prev - obj) <= 1e-11 * obj) stop = 1;
-      eta = fmax(floor_now, 0.5 * eta);
-    }
-    work[L.state + 3] = fmax(floor_now, 0.0);
-    work[L.state + 1] = obj;
-    work[L.state + 0] = eta;
-  }
-  __syncthreads();
-  if (last || stop) {  // evaluation-only pass, or converged: keep x
-    if (tid == 0 && stop) work[L.state + 2] = 1.0;
-    return;
-  }
-  // Jacobi equilibration: G~ = S G S, rhs~ = S rhs with S = diag(1/sqrt(G_jj)),
-  // so column scales of the weighted design do not enter the conditioning;
-  // then Cholesky G~ = L L^T (in place, lower) and two triangular solves.
-  __shared__ double sc[kIrlsMaxD];
-  for (int k = tid; k < d; k += kIrlsThreads) {
-    const double g = G[k * d + k];
-    sc[k] = g > 0.0 ? 1.0 / sqrt(g) : 1.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < d * d; e += kIrlsThreads) G[e] *= sc[e / d] * sc[e % d];
-  for (int k = tid; k < d; k += kIrlsThreads) rhs[k] *= sc[k];
-  __syncthreads();
-  for (int k = 0; k < d; ++k) {
-    if (tid == 0) {
-      const double gkk = G[k * d + k];
-      if (!(gkk > 1e-15)) bad = 1;
-      piv = sqrt(fmax(gkk, 1e-300));
-      G[k * d + k] = piv;
-    }
-    __syncthreads();
-    for (int i = k + 1 + tid; i < d; i += kIrlsThreads) G[i * d + k] /= piv;
-    __syncthreads();
-    for (int e = tid; e < (d - k - 1) * (d - k - 1); e += kIrlsThreads) {
-      const int i = k + 1 + e / (d - k - 1), j = k + 1 + e % (d - k - 1);
-      if (j <= i) G[i * d + j] -= G[i * d + k] * G[j * d + k];
-    }
-    __syncthreads();
-  }
-  // forward solve L y = rhs (column sweep), then L^T z = y; x = S z
-  for (int k = 0; k < d; ++k) {
-    if (tid == 0) rhs[k] /= G[k * d + k];
-    __syncthreads();
-    for (int i = k + 1 + tid; i < d; i += kIrlsThreads) rhs[i] -= G[i * d + k] * rhs[k];
-    __syncthreads();
-  }
-  for (int k = d - 1; k >= 0; --k) {
-    if (tid == 0) rhs[k] /= G[k * d + k];
-    __syncthreads();
-    for (int i = tid; i < k; i += kIrlsThreads) rhs[i] -= G[k * d + i] * rhs[k];
-    __syncthreads();
-  }
-  if (bad) {
-    if (tid == 0) {
-      *status = -4;
-      work[L.state + 2] = 1.0;
-    }
-  } else {
-    for (int i = tid; i < d; i += kIrlsThreads) work[L.x + i] = rhs[i] * sc[i];
-  }
+// Inverse of a 4x4 symmetric positive definite block (row-major in, out) by
+// its Cholesky factor: D^-1 = L^-T L^-1.  Returns false if a pivot of the
+// factorization is not positive.
+__device__ inline bool spd4_inverse(const double* a, double* inv) {
+  const double r0 = rsqrt_f64(fmax(a[0], 1e-300));
+  const double l10 = a[4] * r0, l20 = a[8] * r0, l30 = a[12] * r0;
+  const double p1 = a[5] - l10 * l10;
+  const double r1 = rsqrt_f64(fmax(p1, 1e-300));
+  const double l21 = (a[9] - l20 * l10) * r1, l31 = (a[13] - l30 * l10) * r1;
+  const double p2 = a[10] - l20 * l20 - l21 * l21;
+  const double r2 = rsqrt_f64(fmax(p2, 1e-300));
+  const double l32 = (a[14] - l30 * l20 - l31 * l21) * r2;
+  const double p3 = a[15] - l30 * l30 - l31 * l31 - l32 * l32;
+  const double r3 = rsqrt_f64(fmax(p3, 1e-300));
+  // M = L^-1 (lower): diagonal r_i
+  const double m10 = -l10 * r0 * r1;
+  const double m21 = -l21 * r1 * r2;
+  const double m20 = -(l20 * r0 + l21 * m10) * r2;
+  const double m32 = -l32 * r2 * r3;
+  const double m31 = -(l31 * r1 + l32 * m21) * r3;
+  const double m30 = -(l30 * r0 + l31 * m10 + l32 * m20) * r3;
+  // D^-1 = M^T M
+  inv[0] = r0 * r0 + m10 * m10 + m20 * m20 + m30 * m30;
+  inv[1] = m10 * r1 + m20 * m21 + m30 * m31;
+  inv[2] = m20 * r2 + m30 * m32;
+  inv[3] = m30 * r3;
+  inv[5] = r1 * r1 + m21 * m21 + m31 * m31;
+  inv[6] = m21 * r2 + m31 * m32;
+  inv[7] = m31 * r3;
+  inv[10] = r2 * r2 + m32 * m32;
+  inv[11] = m32 * r3;
+  inv[15] = r3 * r3;
+  inv[4] = inv[1];
+  inv[8] = inv[2];
+  inv[9] = inv[6];
+  inv[12] = inv[3];
+  inv[13] = inv[7];
+  inv[14] = inv[11];
+  return a[0] > 1e-15 && p1 > 1e-15 && p2 > 1e-15 && p3 > 1e-15;
 }
 
-__global__ void __launch_bounds__(1024) irls_init_kernel(int d, const double* __restrict__ w,
-                                                         const int64_t* S_dev, int64_t cap,
-                                                         double* work) {
-  const IrlsLayout L(d);
-  __shared__ double red[16];
-  const int64_t S = min(*S_dev, cap);
+template <typename T>
+__global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int flag_stop, flag_bad, flag_ok;
+  const IrlsGeom g(a.d, sizeof(T));
+  const int d = g.d, q = g.q, W = g.W, NB = g.NB, nbp = g.nbp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* G = reinterpret_cast<double*>(smem);  // Gram, or group partials before the barrier
+  double* rhs = G + g.gdoubles;
+  double* xs = rhs + 64;    // 72: x, then -1 at d, zeros to the padded width
+  double* sc = xs + 72;     // 80: d + 1 scales
+  double* misc = sc + 80;   // [0] sum w, [1] eta, [2] prev obj, [3] floor, [5] obj, [8..11] waves
+  double* gjcol = misc + 16;     // 64 x 4: pivot columns of the Gauss-Jordan step
+  double* gjrow = gjcol + 256;   // 65 x 4: pivot rows, transposed
+  double* gjt = gjrow + 264;     // 65 x 4: D^-1 times the pivot rows, transposed
+  double* gjz = gjt + 264;       // 64: solution
+  double* gjd = gjz + 64;        // 256: per-thread dummy slots
+  double* om = reinterpret_cast<double*>(smem + g.fixed_bytes);
+  T* zr = reinterpret_cast<T*>(om + g.rmax);
+  const T* At = (const T*)a.At;
+  const T* bt = (const T*)a.bt;
+  const int64_t S = min(*a.S_dev, a.cap);
+  // active workgroups: about kIrlsRowTarget rows each, never more than fit in
+  // LDS unless even the whole grid cannot hold them (then rows stream through)
+  int64_t pa = (S + kIrlsRowTarget - 1) / kIrlsRowTarget;
+  const int64_t pmin = (S + g.rmax - 1) / g.rmax;
+  if (pa < pmin) pa = pmin;
+  if (pa > (int64_t)gridDim.x) pa = gridDim.x;
+  if (pa < 1) pa = 1;
+  const int P = (int)pa;
+  if ((int)blockIdx.x >= P) return;
+  const int64_t per = (S + P - 1) / P;
+  const int64_t lo = min(S, (int64_t)blockIdx.x * per), hi = min(S, lo + per);
+  const bool resident = hi - lo <= g.rmax;
+
+  // sum of weights, in the same order in every workgroup
   double sw = 0.0;
-  for (int64_t k = threadIdx.x; k < S; k += blockDim.x) sw += w[k];
+  for (int64_t k = tid; k < S; k += kIrlsThreads) sw += a.w[k];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) sw += __shfl_xor(sw, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sw;
-  if (threadIdx.x < d) work[L.x + threadIdx.x] = 0.0;
+  if (lane == 0) misc[8 + wave] = sw;
+  if (tid < 72) xs[tid] = tid == d ? -1.0 : 0.0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
-    work[L.state + 0] = 0.0;
-    work[L.state + 1] = 0.0;
-    work[L.state + 2] = 0.0;
-    work[L.state + 3] = 0.0;
-    work[L.state + 4] = t > 0.0 ? t : 1.0;
-    work[L.state + 5] = 0.0;
+  if (tid == 0) {
+    const double t = misc[8] + misc[9] + misc[10] + misc[11];
+    misc[0] = t > 0.0 ? t : 1.0;
+    misc[1] = 0.0;
+    misc[2] = 0.0;
+    misc[3] = 0.0;
+  }
+
+  // this thread's 4x4 block (bi <= bj) of the Gram and its share of the rows
+  const int pair = tid % nbp, grp = tid / nbp;
+  const bool gram_thread = grp < g.groups;
+  int bi, bj;
+  block_pair(pair, NB, bi, bj);
+
+  for (int it = 0;; ++it) {
+    __syncthreads();
+    const double eta = misc[1];
+    double acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+    double objp = 0.0;
+    for (int64_t c0 = lo; c0 < hi; c0 += g.rmax) {
+      const int nr = (int)min<int64_t>(g.rmax, hi - c0);
+      if (!resident || it == 0) {
+        __syncthreads();
+        for (int r0 = 0; r0 < nr; r0 += 64) {
+          const int r = r0 + lane;
+          for (int c = wave; c < W; c += 4) {
+            T v = (T)0;
+            if (r < nr && c < q) v = c < d ? At[c0 + r + (int64_t)c * a.ldat] : bt[c0 + r];
+            zr[r * W + c] = v;
+          }
+        }
+        __syncthreads();
+      }
+      // residuals at x, objective, IRLS weights
+      for (int r = tid; r < nr; r += kIrlsThreads) {
+        const T* z = zr + r * W;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+        for (int c = 0; c < W; c += 4) {
+          double zv[4];
+          load4<T>(z + c, zv);
+          const double2 x01 = *reinterpret_cast<const double2*>(xs + c);
+          const double2 x23 = *reinterpret_cast<const double2*>(xs + c + 2);
+          s4[0] = fma(zv[0], x01.x, s4[0]);
+          s4[1] = fma(zv[1], x01.y, s4[1]);
+          s4[2] = fma(zv[2], x23.x, s4[2]);
+          s4[3] = fma(zv[3], x23.y, s4[3]);
+        }
+        // xs[d] = -1 and xs[d+1..W) = 0, so the sum is a^T x - b
+        const double res = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        const double wk = a.w[c0 + r];
+        objp += wk * fabs(res);
+        om[r] = eta > 0.0 ? wk / sqrt(res * res + eta * eta) : wk;
+      }
+      __syncthreads();
+      if (gram_thread && grp < nr) {
+        // one row ahead: the loads of row rr + groups are issued before the
+        // products of row rr (the clamped index keeps them in bounds)
+        double av[4], bv[4], o;
+        load4<T>(zr + grp * W + 4 * bi, av);
+        load4<T>(zr + grp * W + 4 * bj, bv);
+        o = om[grp];
+        for (int rr = grp; rr < nr; rr += g.groups) {
+          const int rn = min(rr + g.groups, nr - 1);
+          double an[4], bn[4];
+          load4<T>(zr + rn * W + 4 * bi, an);
+          load4<T>(zr + rn * W + 4 * bj, bn);
+          const double on = om[rn];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double oa = o * av[i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[4 * i + j] = fma(oa, bv[j], acc[4 * i + j]);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            av[i] = an[i];
+            bv[i] = bn[i];
+          }
+          o = on;
+        }
+      }
+      if (!resident) __syncthreads();
+    }
+    // workgroup partial: sum the row groups in order, then publish
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) objp += __shfl_xor(objp, o, 64);
+    if (lane == 0) misc[8 + wave] = objp;
+    if (gram_thread)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) G[(grp * nbp + pair) * 16 + e] = acc[e];
+    __syncthreads();
+    double* mine = a.part + ((size_t)(it & 1) * P + blockIdx.x) * g.pstride;
+    for (int e = tid; e < nbp * 16; e += kIrlsThreads) {
+      double s = 0.0;
+      for (int gg = 0; gg < g.groups; ++gg) s += G[gg * nbp * 16 + e];
+      mine[e] = s;
+    }
+    if (tid == 0) mine[nbp * 16] = misc[8] + misc[9] + misc[10] + misc[11];
+    if (!grid_barrier(a.bar, (unsigned)(it + 1) * (unsigned)P, &flag_ok)) {
+      if (blockIdx.x == 0 && tid == 0) *a.status = -5;
+      break;
+    }
+    // all partials, fixed order, into the symmetric G and rhs; the loads of up
+    // to four entries x sixteen partials are issued before any is summed
+    const double* pb = a.part + (size_t)(it & 1) * P * g.pstride;
+    for (int e0 = tid; e0 < g.E; e0 += 4 * kIrlsThreads) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int p0 = 0; p0 < P; p0 += 16) {
+        double v[4][16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int e = e0 + k * kIrlsThreads, p = p0 + u;
+            v[k][u] = (e < g.E && p < P) ? pb[(size_t)p * g.pstride + e] : 0.0;
+          }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int u = 0; u < 16; ++u) s[k] += v[k][u];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = e0 + k * kIrlsThreads;
+        if (e >= g.E) continue;
+        if (e == g.E - 1) {
+          misc[5] = s[k];
+          continue;
+        }
+        int pbi, pbj;
+        block_pair(e >> 4, NB, pbi, pbj);
+        const int ii = (e >> 2) & 3, jj = e & 3;
+        if (pbi == pbj && ii > jj) continue;
+        const int row = 4 * pbi + ii, col = 4 * pbj + jj;
+        if (row < d && col < d) {
+          G[row * d + col] = s[k];
+          G[col * d + row] = s[k];
+        } else if (row < d && col == d) {
+          rhs[row] = s[k];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double obj = misc[5];
+      double e_c = misc[1];
+      const double floor_now = 1e-9 * obj / misc[0];
+      int stop = 0;
+      if (e_c <= 0.0) {
+        e_c = obj / misc[0];  // first smoothing level: mean weighted residual
+      } else {
+        if (e_c <= misc[3] * 1.0000001 && fabs(misc[2] - obj) <= 1e-9 * obj) stop = 1;
+        e_c = fmax(floor_now, 0.3 * e_c);
+      }
+      if (!(obj > 0.0) || it >= a.iters) stop = 1;  // exact fit, non-finite, or budget spent
+      misc[3] = floor_now;
+      misc[2] = obj;
+      misc[1] = e_c;
+      flag_stop = stop;
+      flag_bad = 0;
+    }
+    __syncthreads();
+    if (flag_stop) break;
+    // Jacobi equilibration S = diag(G)^-1/2, then block Gauss-Jordan on the
+    // augmented n4 x (n4 + 1) system [S G S | S rhs] (identity rows and
+    // columns pad d to n4, a multiple of 4).  Thread tid keeps entries
+    // e = tid + threads * u in registers.  Step K: the pivot block's columns
+    // and rows are published to LDS; D^-1 of the 4x4 pivot block gives
+    // T = D^-1 (pivot rows); pivot rows become T and every other row r loses
+    // M[r, P] T.  After the last step the last column holds z, x = S z.
+    if (tid < d) {
+      const double gg = G[tid * d + tid];
+      sc[tid] = gg > 0.0 ? rsqrt_f64(gg) : 1.0;
+    }
+    __syncthreads();
+    {
+      const int n4 = (d + 3) & ~3, nc = n4 + 1, ne = (n4 * nc + kIrlsThreads - 1) / kIrlsThreads;
+      double mv[kGjMax];
+      int er[kGjMax], ec[kGjMax];
+#pragma unroll
+      for (int u = 0; u < kGjMax; ++u) {
+        er[u] = -1;
+        ec[u] = -1;
+        mv[u] = 0.0;
+        if (u < ne) {
+          const int e = tid + kIrlsThreads * u;
+          if (e < n4 * nc) {
+            const int r = e / nc, c = e - r * nc;
+            er[u] = r;
+            ec[u] = c;
+            double v;
+            if (c == n4) v = r < d ? rhs[r] * sc[r] : 0.0;
+            else if (r < d && c < d) v = G[r * d + c] * sc[r] * sc[c];
+            else v = r == c ? 1.0 : 0.0;
+            mv[u] = v;
+          }
+        }
+      }
+      double* dummy = gjd + tid;
+      bool ok = true;
+      for (int K = 0; K < n4 / 4; ++K) {
+        const int p0 = 4 * K;
+        // publish pivot columns (colP[r][m] = M[r][p0+m]) and rows (rowT[c][m] = M[p0+m][c])
+#pragma unroll
+        for (int u = 0; u < kGjMax; ++u) {
+          if (u < ne) {
+            const int r = er[u], c = ec[u];
+            const bool inc = r >= 0 && (unsigned)(c - p0) < 4u;
+            const bool inr = r >= 0 && (unsigned)(r - p0) < 4u;
+            *(inc ? gjcol + r * 4 + (c - p0) : dummy) = mv[u];
+            *(inr ? gjrow + c * 4 + (r - p0) : dummy) = mv[u];
+          }
+        }
+        __syncthreads();
+        if (tid < nc) {
+          double Dm[16], Di[16];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) Dm[e] = gjcol[(p0 + (e >> 2)) * 4 + (e & 3)];
+          ok = spd4_inverse(Dm, Di) && ok;
+          const double2 q01 = *reinterpret_cast<const double2*>(gjrow + tid * 4);
+          const double2 q23 = *reinterpret_cast<const double2*>(gjrow + tid * 4 + 2);
+          const double q[4] = {q01.x, q01.y, q23.x, q23.y};
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            gjt[tid * 4 + m] = Di[4 * m] * q[0] + Di[4 * m + 1] * q[1] + Di[4 * m + 2] * q[2] +
+                               Di[4 * m + 3] * q[3];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kGjMax; ++u) {
+          if (u < ne) {
+            const int r = er[u] >= 0 ? er[u] : 0, c = ec[u] >= 0 ? ec[u] : 0;
+            const double2 t01 = *reinterpret_cast<const double2*>(gjt + c * 4);
+            const double2 t23 = *reinterpret_cast<const double2*>(gjt + c * 4 + 2);
+            const double2 a01 = *reinterpret_cast<const double2*>(gjcol + r * 4);
+            const double2 a23 = *reinterpret_cast<const double2*>(gjcol + r * 4 + 2);
+            const double upd = mv[u] - (a01.x * t01.x + a01.y * t01.y + a23.x * t23.x + a23.y * t23.y);
+            const int rm = r - p0;
+            const double tp = rm == 0 ? t01.x : rm == 1 ? t01.y : rm == 2 ? t23.x : t23.y;
+            mv[u] = (unsigned)rm < 4u ? tp : upd;
+          }
+        }
+        __syncthreads();
+      }
+      if (!ok) flag_bad = 1;
+#pragma unroll
+      for (int u = 0; u < kGjMax; ++u)
+        if (u < ne && ec[u] == n4 && er[u] >= 0 && er[u] < d) gjz[er[u]] = mv[u];
+      __syncthreads();
+      if (!flag_bad && tid < d) xs[tid] = gjz[tid] * sc[tid];
+    }
+    __syncthreads();
+    if (flag_bad) {
+      if (blockIdx.x == 0 && tid == 0) *a.status = -4;
+      break;
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < d) a.x_out[tid] = xs[tid];
+    if (tid == 0 && a.obj_out) *a.obj_out = misc[2];
   }
 }
 
-__global__ void irls_out_kernel(int d, const double* work, double* x_out, double* obj_out) {
-  const IrlsLayout L(d);
-  if (threadIdx.x < d) x_out[threadIdx.x] = work[L.x + threadIdx.x];
-  if (threadIdx.x == 0 && obj_out) *obj_out = work[L.state + 5];
+__global__ void irls_reset_kernel(unsigned* bar) {
+  if (threadIdx.x < 2) bar[threadIdx.x] = 0u;
+}
+
+int irls_workgroups(int64_t S_hint) {
+  int64_t p = (S_hint + kIrlsRowTarget - 1) / kIrlsRowTarget;
+  if (const char* e = std::getenv("FCTL1_IRLS_WGS")) p = std::atoi(e);
+  if (p < 1) p = 1;
+  if (p > kIrlsMaxWgs) p = kIrlsMaxWgs;
+  return (int)p;
 }
 
 hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,
-                       int64_t cap, int d, int64_t ldat, bool f64, int iters, double* work,
-                       double* x_out, double* obj_out, int* status, hipStream_t st) {
+                       int64_t cap, int64_t S_hint, int d, int64_t ldat, bool f64, int iters,
+                       double* work, double* x_out, double* obj_out, int* status,
+                       hipStream_t st) {
   if (d > kIrlsMaxD || d < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(irls_init_kernel, dim3(1), dim3(1024), 0, st, d, w, S_dev, cap, work);
-  for (int it = 0; it <= iters; ++it) {
-    const int last = it == iters;
-    if (f64)
-      hipLaunchKernelGGL(irls_gram_kernel<double>, dim3(kIrlsWgs), dim3(kIrlsThreads), 0, st,
-                         (const double*)At, (const double*)bt, w, S_dev, cap, d, ldat, work);
-    else
-      hipLaunchKernelGGL(irls_gram_kernel<float>, dim3(kIrlsWgs), dim3(kIrlsThreads), 0, st,
-                         (const float*)At, (const float*)bt, w, S_dev, cap, d, ldat, work);
-    hipLaunchKernelGGL(irls_solve_kernel, dim3(1), dim3(kIrlsThreads), 0, st, d, work, last,
-                       status);
-  }
-  hipLaunchKernelGGL(irls_out_kernel, dim3(1), dim3(128), 0, st, d, work, x_out, obj_out);
-  return hipGetLastError();
+  const IrlsGeom g(d, f64 ? sizeof(double) : sizeof(float));
+  const int P = irls_workgroups(S_hint);
+  IrlsArgs a;
+  a.At = At;
+  a.bt = bt;
+  a.w = w;
+  a.S_dev = S_dev;
+  a.cap = cap;
+  a.ldat = ldat;
+  a.d = d;
+  a.iters = iters;
+  a.part = work;
+  a.bar = reinterpret_cast<unsigned*>(work + irls_work_doubles(0, d) - 8);
+  a.x_out = x_out;
+  a.obj_out = obj_out;
+  a.status = status;
+  const size_t lds = g.lds_bytes();
+  const void* fn = f64 ? (const void*)irls_kernel<double> : (const void*)irls_kernel<float>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(irls_reset_kernel, dim3(1), dim3(64), 0, st, a.bar);
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(fn, dim3(P), dim3(kIrlsThreads), args, (unsigned)lds, st);
 }
 
 }  // namespace fctl1

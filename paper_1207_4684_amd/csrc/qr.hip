@@ -80,11 +80,11 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(const double* __re
         if (lane == 0) wdot[j] = dot * beta;
       }
       __syncthreads();
-      // P[i, j] -= v_i w_j over all trailing (i, j) pairs
-      const int rows = m - k, cols = q - k - 1;
-      for (int e = tid; e < rows * cols; e += kQrThreads) {
-        const int i = k + e % rows, j = k + 1 + e / rows;
-        Pm[i + (size_t)j * m] -= colk[i] * wdot[j];
+      // P[i, j] -= v_i w_j: one wave per trailing column, lanes over rows
+      for (int j = k + 1 + wave; j < q; j += nw) {
+        double* colj = Pm + (size_t)j * m;
+        const double wj = wdot[j];
+        for (int i = k + lane; i < m; i += 64) colj[i] -= colk[i] * wj;
       }
     }
     __syncthreads();
@@ -169,43 +169,54 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// M = R^-1 Pi2 by back substitution, one thread per column of Pi2.
-__global__ void form_m_kernel(const double* __restrict__ R, int q, int r2, int ldm, uint64_t seed,
-                              uint32_t instance, double* __restrict__ Md, float* __restrict__ Mf,
-                              float* __restrict__ Mfb, uint16_t* __restrict__ Mb,
-                              int* __restrict__ status) {
-  const int c = threadIdx.x;
-  if (c >= ldm) return;
-  if (c >= r2) {  // zero padding columns
-    for (int a = 0; a < q; ++a) {
-      Md[a * ldm + c] = 0.0;
-      if (Mf) Mf[a * ldm + c] = 0.0f;
-      if (Mfb) Mfb[a * ldm + c] = 0.0f;
-      if (Mb) Mb[a * ldm + c] = 0;
+// M = R^-1 Pi2: Pi2 is drawn by all threads into LDS, then one thread per
+// column of Pi2 back-substitutes against R held in LDS.
+__global__ void __launch_bounds__(256) form_m_kernel(const double* __restrict__ R, int q, int r2,
+                                                     int ldm, uint64_t seed, uint32_t instance,
+                                                     double* __restrict__ Md, float* __restrict__ Mf,
+                                                     float* __restrict__ Mfb,
+                                                     uint16_t* __restrict__ Mb,
+                                                     int* __restrict__ status) {
+  __shared__ double Rs[96 * 96];
+  __shared__ double Ms[96 * 32];
+  for (int e = threadIdx.x; e < q * q; e += blockDim.x) Rs[e] = R[e];
+  for (int e = threadIdx.x; e < q * ldm; e += blockDim.x) {
+    const int a = e / ldm, c = e % ldm;
+    double v = 0.0;
+    if (c < r2) {
+      const uint4 w = stream_words(seed, kStreamPi2, (uint64_t)a * r2 + c, instance);
+      v = cauchy_from_word_f64(w.x);
     }
-    return;
+    Ms[e] = v;
   }
-  for (int a = q - 1; a >= 0; --a) {
-    const uint4 w = stream_words(seed, kStreamPi2, (uint64_t)a * r2 + c, instance);
-    double v = cauchy_from_word_f64(w.x);
-    for (int bcol = a + 1; bcol < q; ++bcol) v -= R[a + (int64_t)bcol * q] * Md[bcol * ldm + c];
-    v = v / R[a + (int64_t)a * q];
-    if (!isfinite(v)) *status = -4;
-    Md[a * ldm + c] = v;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < r2) {
+    for (int a = q - 1; a >= 0; --a) {
+      double v = Ms[a * ldm + c];
+      for (int bcol = a + 1; bcol < q; ++bcol) v -= Rs[a + bcol * q] * Ms[bcol * ldm + c];
+      v = v / Rs[a + a * q];
+      if (!isfinite(v)) *status = -4;
+      Ms[a * ldm + c] = v;
+    }
   }
-  for (int a = 0; a < q; ++a) {
-    const float f = (float)Md[a * ldm + c];
+  __syncthreads();
+  for (int e = threadIdx.x; e < q * ldm; e += blockDim.x) {
+    const double v = Ms[e];
+    const float f = (float)v;
     const uint16_t h = f32_to_bf16_rne(f);
-    if (Mf) Mf[a * ldm + c] = f;
-    if (Mfb) Mfb[a * ldm + c] = __uint_as_float((uint32_t)h << 16);
-    if (Mb) Mb[a * ldm + c] = h;
+    Md[e] = v;
+    if (Mf) Mf[e] = f;
+    if (Mfb) Mfb[e] = __uint_as_float((uint32_t)h << 16);
+    if (Mb) Mb[e] = h;
   }
 }
 
 hipError_t launch_form_m(const double* R, int q, int r2, int ldm, uint64_t seed,
                          uint32_t instance, double* Md, float* Mf, float* Mfb, uint16_t* Mb,
                          int* status, hipStream_t st) {
-  hipLaunchKernelGGL(form_m_kernel, dim3(1), dim3(64), 0, st, R, q, r2, ldm, seed, instance, Md,
+  if (q > 96 || ldm > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(form_m_kernel, dim3(1), dim3(256), 0, st, R, q, r2, ldm, seed, instance, Md,
                      Mf, Mfb, Mb, status);
   return hipGetLastError();
 }
