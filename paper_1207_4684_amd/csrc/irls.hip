@@ -48,7 +48,7 @@ struct IrlsGeom {
     pstride = (E + 7) & ~7;
     const size_t g1 = (size_t)d * d, g2 = (size_t)groups * nbp * 16;
     gdoubles = ((g1 > g2 ? g1 : g2) + 1) & ~(size_t)1;  // keeps the vectors 16-byte aligned
-    fixed_bytes = (((gdoubles + 64 + 72 + 80 + 16 + 256 + 264 + 264 + 64 + 256) * sizeof(double)) + 15) &
+    fixed_bytes = (((gdoubles + 64 + 72 + 80 + 16 + 512 + 528 + 264 + 64 + 256) * sizeof(double)) + 15) &
                   ~(size_t)15;
     row_bytes = (size_t)W * elem + sizeof(double);
     rmax = (int)((kIrlsLdsBytes - fixed_bytes) / row_bytes);
@@ -68,6 +68,7 @@ struct IrlsArgs {
   int64_t ldat;
   int d;
   int iters;
+  int row_target;  // coreset rows per active workgroup
   double* part;   // 2 x gridDim.x x pstride
   unsigned* bar;  // [0] arrival counter (zero at launch), [1] abort flag
   double* x_out;
@@ -116,13 +117,6 @@ __device__ inline void block_pair(int pr, int NB, int& bi, int& bj) {
   }
   bi = i;
   bj = i + rem;
-}
-
-__device__ inline double readlane_f64(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
@@ -194,6 +188,112 @@ __device__ inline bool spd4_inverse(const double* a, double* inv) {
   return a[0] > 1e-15 && p1 > 1e-15 && p2 > 1e-15 && p3 > 1e-15;
 }
 
+// Block Gauss-Jordan on the Jacobi-scaled augmented system
+// [S G S | S rhs] (n4 x (n4 + 1), identity rows and columns pad d to n4, a
+// multiple of 4), all threads of the workgroup; thread tid keeps entries
+// (er[u], ec[u]), u < NE, in registers.  Step K publishes the pivot block's
+// columns and rows (double-buffered by step parity), forms T = D^-1 (pivot
+// rows) with D the 4x4 pivot block, then pivot rows become T and every other
+// row r loses M[r, P] T.  The last column ends as z with (S G S) z = S rhs;
+// it is written to z[0..d).  Returns false if a pivot block is not positive
+// definite.
+template <int NE>
+__device__ __forceinline__ bool gj_solve(const int* er, const int* ec, const double* G,
+                                         const double* rhs, const double* sc, double* gjcol2,
+                                         double* gjrow2, double* gjt, double* gjd, int d,
+                                         double* z) {
+  const int tid = threadIdx.x;
+  const int n4 = (d + 3) & ~3, nc = n4 + 1;
+  double mv[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int r = er[u], c = ec[u];
+    double v = 0.0;
+    if (r >= 0) {
+      if (c == n4) v = r < d ? rhs[r] * sc[r] : 0.0;
+      else if (r < d && c < d) v = G[r * d + c] * sc[r] * sc[c];
+      else v = r == c ? 1.0 : 0.0;
+    }
+    mv[u] = v;
+  }
+  double* dummy = gjd + tid;
+  bool ok = true;
+  for (int K = 0; K < n4 / 4; ++K) {
+    const int p0 = 4 * K;
+    double* gjcol = gjcol2 + (K & 1) * 256;  // gjcol[r][m] = M[r][p0 + m]
+    double* gjrow = gjrow2 + (K & 1) * 264;  // gjrow[c][m] = M[p0 + m][c]
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int r = er[u], c = ec[u];
+      const bool inc = r >= 0 && (unsigned)(c - p0) < 4u;
+      const bool inr = r >= 0 && (unsigned)(r - p0) < 4u;
+      *(inc ? gjcol + r * 4 + (c - p0) : dummy) = mv[u];
+      *(inr ? gjrow + c * 4 + (r - p0) : dummy) = mv[u];
+    }
+    __syncthreads();
+    if (tid < nc) {
+      double Dm[16], Di[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) Dm[e] = gjcol[(p0 + (e >> 2)) * 4 + (e & 3)];
+      ok = spd4_inverse(Dm, Di) && ok;
+      const double2 q01 = *reinterpret_cast<const double2*>(gjrow + tid * 4);
+      const double2 q23 = *reinterpret_cast<const double2*>(gjrow + tid * 4 + 2);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        gjt[tid * 4 + m] = Di[4 * m] * q01.x + Di[4 * m + 1] * q01.y + Di[4 * m + 2] * q23.x +
+                           Di[4 * m + 3] * q23.y;
+    }
+    __syncthreads();
+    // loads of a chunk of entries are issued together, then their updates
+    constexpr int CH = NE < 5 ? NE : 5;
+#pragma unroll
+    for (int u0 = 0; u0 < NE; u0 += CH) {
+      double2 t01[CH], t23[CH], a01[CH], a23[CH];
+#pragma unroll
+      for (int v = 0; v < CH; ++v) {
+        const int u = u0 + v < NE ? u0 + v : NE - 1;
+        const int r = er[u] >= 0 ? er[u] : 0, c = ec[u];
+        t01[v] = *reinterpret_cast<const double2*>(gjt + c * 4);
+        t23[v] = *reinterpret_cast<const double2*>(gjt + c * 4 + 2);
+        a01[v] = *reinterpret_cast<const double2*>(gjcol + r * 4);
+        a23[v] = *reinterpret_cast<const double2*>(gjcol + r * 4 + 2);
+      }
+#pragma unroll
+      for (int v = 0; v < CH; ++v) {
+        const int u = u0 + v;
+        if (u < NE) {
+          const double upd = mv[u] - (a01[v].x * t01[v].x + a01[v].y * t01[v].y +
+                                      a23[v].x * t23[v].x + a23[v].y * t23[v].y);
+          const int rm = er[u] - p0;
+          const double tp =
+              rm == 0 ? t01[v].x : rm == 1 ? t01[v].y : rm == 2 ? t23[v].x : t23[v].y;
+          mv[u] = (unsigned)rm < 4u ? tp : upd;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u)
+    if (ec[u] == n4 && er[u] >= 0 && er[u] < d) z[er[u]] = mv[u];
+  return ok;
+}
+
+// d > 48: kept out of line so that its register demand does not raise the
+// kernel's own.
+__device__ __noinline__ bool gj_solve_wide(const double* G, const double* rhs, const double* sc,
+                                           double* gjcol2, double* gjrow2, double* gjt,
+                                           double* gjd, int d, double* z) {
+  const int n4 = (d + 3) & ~3, nc = n4 + 1;
+  int er[kGjMax], ec[kGjMax];
+#pragma unroll
+  for (int u = 0; u < kGjMax; ++u) {
+    const int e = threadIdx.x + kIrlsThreads * u;
+    er[u] = e < n4 * nc ? e / nc : -1;
+    ec[u] = e < n4 * nc ? e - er[u] * nc : 0;
+  }
+  return gj_solve<kGjMax>(er, ec, G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, z);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -206,9 +306,9 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
   double* xs = rhs + 64;    // 72: x, then -1 at d, zeros to the padded width
   double* sc = xs + 72;     // 80: d + 1 scales
   double* misc = sc + 80;   // [0] sum w, [1] eta, [2] prev obj, [3] floor, [5] obj, [8..11] waves
-  double* gjcol = misc + 16;     // 64 x 4: pivot columns of the Gauss-Jordan step
-  double* gjrow = gjcol + 256;   // 65 x 4: pivot rows, transposed
-  double* gjt = gjrow + 264;     // 65 x 4: D^-1 times the pivot rows, transposed
+  double* gjcol2 = misc + 16;    // 2 x 64 x 4: pivot columns of the Gauss-Jordan step
+  double* gjrow2 = gjcol2 + 512; // 2 x 65 x 4: pivot rows, transposed
+  double* gjt = gjrow2 + 528;    // 65 x 4: D^-1 times the pivot rows, transposed
   double* gjz = gjt + 264;       // 64: solution
   double* gjd = gjz + 64;        // 256: per-thread dummy slots
   double* om = reinterpret_cast<double*>(smem + g.fixed_bytes);
@@ -218,7 +318,7 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
   const int64_t S = min(*a.S_dev, a.cap);
   // active workgroups: about kIrlsRowTarget rows each, never more than fit in
   // LDS unless even the whole grid cannot hold them (then rows stream through)
-  int64_t pa = (S + kIrlsRowTarget - 1) / kIrlsRowTarget;
+  int64_t pa = (S + a.row_target - 1) / a.row_target;
   const int64_t pmin = (S + g.rmax - 1) / g.rmax;
   if (pa < pmin) pa = pmin;
   if (pa > (int64_t)gridDim.x) pa = gridDim.x;
@@ -245,6 +345,20 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
     misc[3] = 0.0;
   }
 
+  // entries of the augmented n4 x (n4 + 1) system owned by this thread in the
+  // Gauss-Jordan solve: e = tid + threads * u
+  const int n4 = (d + 3) & ~3, nc = n4 + 1, ne = (n4 * nc + kIrlsThreads - 1) / kIrlsThreads;
+  int er[10], ec[10];  // d <= 48; wider systems decode their own entries
+#pragma unroll
+  for (int u = 0; u < 10; ++u) {
+    const int e = tid + kIrlsThreads * u;
+    er[u] = -1;
+    ec[u] = 0;  // absent entries read column 0 and publish to the dummy slot
+    if (u < ne && e < n4 * nc) {
+      er[u] = e / nc;
+      ec[u] = e - er[u] * nc;
+    }
+  }
   // this thread's 4x4 block (bi <= bj) of the Gram and its share of the rows
   const int pair = tid % nbp, grp = tid / nbp;
   const bool gram_thread = grp < g.groups;
@@ -416,78 +530,12 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
     }
     __syncthreads();
     {
-      const int n4 = (d + 3) & ~3, nc = n4 + 1, ne = (n4 * nc + kIrlsThreads - 1) / kIrlsThreads;
-      double mv[kGjMax];
-      int er[kGjMax], ec[kGjMax];
-#pragma unroll
-      for (int u = 0; u < kGjMax; ++u) {
-        er[u] = -1;
-        ec[u] = -1;
-        mv[u] = 0.0;
-        if (u < ne) {
-          const int e = tid + kIrlsThreads * u;
-          if (e < n4 * nc) {
-            const int r = e / nc, c = e - r * nc;
-            er[u] = r;
-            ec[u] = c;
-            double v;
-            if (c == n4) v = r < d ? rhs[r] * sc[r] : 0.0;
-            else if (r < d && c < d) v = G[r * d + c] * sc[r] * sc[c];
-            else v = r == c ? 1.0 : 0.0;
-            mv[u] = v;
-          }
-        }
-      }
-      double* dummy = gjd + tid;
-      bool ok = true;
-      for (int K = 0; K < n4 / 4; ++K) {
-        const int p0 = 4 * K;
-        // publish pivot columns (colP[r][m] = M[r][p0+m]) and rows (rowT[c][m] = M[p0+m][c])
-#pragma unroll
-        for (int u = 0; u < kGjMax; ++u) {
-          if (u < ne) {
-            const int r = er[u], c = ec[u];
-            const bool inc = r >= 0 && (unsigned)(c - p0) < 4u;
-            const bool inr = r >= 0 && (unsigned)(r - p0) < 4u;
-            *(inc ? gjcol + r * 4 + (c - p0) : dummy) = mv[u];
-            *(inr ? gjrow + c * 4 + (r - p0) : dummy) = mv[u];
-          }
-        }
-        __syncthreads();
-        if (tid < nc) {
-          double Dm[16], Di[16];
-#pragma unroll
-          for (int e = 0; e < 16; ++e) Dm[e] = gjcol[(p0 + (e >> 2)) * 4 + (e & 3)];
-          ok = spd4_inverse(Dm, Di) && ok;
-          const double2 q01 = *reinterpret_cast<const double2*>(gjrow + tid * 4);
-          const double2 q23 = *reinterpret_cast<const double2*>(gjrow + tid * 4 + 2);
-          const double q[4] = {q01.x, q01.y, q23.x, q23.y};
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-            gjt[tid * 4 + m] = Di[4 * m] * q[0] + Di[4 * m + 1] * q[1] + Di[4 * m + 2] * q[2] +
-                               Di[4 * m + 3] * q[3];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kGjMax; ++u) {
-          if (u < ne) {
-            const int r = er[u] >= 0 ? er[u] : 0, c = ec[u] >= 0 ? ec[u] : 0;
-            const double2 t01 = *reinterpret_cast<const double2*>(gjt + c * 4);
-            const double2 t23 = *reinterpret_cast<const double2*>(gjt + c * 4 + 2);
-            const double2 a01 = *reinterpret_cast<const double2*>(gjcol + r * 4);
-            const double2 a23 = *reinterpret_cast<const double2*>(gjcol + r * 4 + 2);
-            const double upd = mv[u] - (a01.x * t01.x + a01.y * t01.y + a23.x * t23.x + a23.y * t23.y);
-            const int rm = r - p0;
-            const double tp = rm == 0 ? t01.x : rm == 1 ? t01.y : rm == 2 ? t23.x : t23.y;
-            mv[u] = (unsigned)rm < 4u ? tp : upd;
-          }
-        }
-        __syncthreads();
-      }
+      bool ok;
+      if (ne <= 2) ok = gj_solve<2>(er, ec, G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, gjz);
+      else if (ne <= 5) ok = gj_solve<5>(er, ec, G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, gjz);
+      else if (ne <= 10) ok = gj_solve<10>(er, ec, G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, gjz);
+      else ok = gj_solve_wide(G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, gjz);
       if (!ok) flag_bad = 1;
-#pragma unroll
-      for (int u = 0; u < kGjMax; ++u)
-        if (u < ne && ec[u] == n4 && er[u] >= 0 && er[u] < d) gjz[er[u]] = mv[u];
       __syncthreads();
       if (!flag_bad && tid < d) xs[tid] = gjz[tid] * sc[tid];
     }
@@ -508,8 +556,15 @@ __global__ void irls_reset_kernel(unsigned* bar) {
   if (threadIdx.x < 2) bar[threadIdx.x] = 0u;
 }
 
-int irls_workgroups(int64_t S_hint) {
-  int64_t p = (S_hint + kIrlsRowTarget - 1) / kIrlsRowTarget;
+static int irls_row_target() {
+  int r = kIrlsRowTarget;
+  if (const char* e = std::getenv("FCTL1_IRLS_ROWS")) r = std::atoi(e);
+  return r < 16 ? 16 : r;
+}
+
+static int irls_workgroups(int64_t S_hint) {
+  const int rt = irls_row_target();
+  int64_t p = (S_hint + rt - 1) / rt;
   if (const char* e = std::getenv("FCTL1_IRLS_WGS")) p = std::atoi(e);
   if (p < 1) p = 1;
   if (p > kIrlsMaxWgs) p = kIrlsMaxWgs;
@@ -532,6 +587,7 @@ hipError_t launch_irls(const void* At, const void* bt, const double* w, const in
   a.ldat = ldat;
   a.d = d;
   a.iters = iters;
+  a.row_target = irls_row_target();
   a.part = work;
   a.bar = reinterpret_cast<unsigned*>(work + irls_work_doubles(0, d) - 8);
   a.x_out = x_out;
