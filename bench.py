@@ -9,8 +9,10 @@ Inputs are resident in HBM before the timed region.
 value = algorithmic bytes of the two streaming passes (X read twice, lambda
 written once) per step / step time.  The dominant kernel's roofline entry
 uses the pass-1 kernel's own device time, measured with HIP events around its
-launches on the stream it runs on.  The CPU oracle is timed on a bounded
-sample of the same workload on the host.
+launches on the stream it runs on; its HBM traffic comes from the committed
+counter summary when that summary was taken on the current kernel source.
+The CPU oracle runs the whole path (steps 1-8) once on the same workload on
+one host core.
 """
 from __future__ import annotations
 
@@ -29,25 +31,37 @@ METRIC = "Π1A + sampling pass GB/s (% HBM peak); ℓ1 solve time at (1+ε) opt,
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_oracle_sample(A, b, w, rows: int):
-    """Time the oracle's steps 1-7 on the first `rows` rows, one thread."""
+def cpu_oracle_run(A, b, w, rows: int):
+    """Time the oracle's whole path (steps 1-8) on the first `rows` rows, one thread."""
     from threadpoolctl import threadpool_limits
-    from oracle import basis, fct, pipeline, sampling
+    from oracle import pipeline
+    rows = min(rows, w.n)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        X = pipeline.form_x(A[:, :rows].T, b[:rows])
-        Y = fct.pi1_apply(X, w.s, w.r1, w.seed)
-        R = basis.qr_r(Y)
-        M = basis.m_matrix(R, w.seed, w.r2)
-        lam = sampling.row_norm_estimates(X, M)
-        p = sampling.probabilities(lam, w.s_out)
-        sampling.select(p, w.seed)
+        out = pipeline.l1_regress(A[:, :rows].T, b[:rows], s=w.s, r1=w.r1, r2=w.r2,
+                                  s_out=w.s_out, seed=w.seed)
         dt = time.perf_counter() - t0
     q = w.d + 1
     nbytes = 2 * rows * q * 4 + rows * 4
     return dict(value=nbytes / dt / 1e9, unit="GB/s", cores=1, kind="oracle",
-                sample=f"first {rows} of {w.n} rows, steps 1-7 (sketch, QR, row norms, selection), "
-                       f"{dt:.2f} s")
+                sample=f"{rows} of {w.n} rows, steps 1-8 (sketch, QR, row norms, selection, "
+                       f"coreset LP of {out['idx'].size} rows), {dt:.2f} s")
+
+
+def committed_traffic(kernel_sources_sha: str, path: str):
+    """HBM bytes per pass-1 launch from the committed counter summary, or None
+    if it is missing or was taken on other kernel source."""
+    try:
+        with open(path) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines() if ": " in line)
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != kernel_sources_sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -55,7 +69,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-rows", type=int, default=1 << 21)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 22)
+    ap.add_argument("--profile-copy-mib", type=int, default=0,
+                    help="after timing, copy this many MiB device to device (counter scale)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solve")
     args = ap.parse_args()
@@ -69,9 +85,13 @@ def main():
     import synth
     from paper_1207_4684_amd import fctl1 as F
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     w = synth.TALL
     q = w.d + 1
     A, b, _ = synth.generate(w)
+    progress(f"generated {w.name}")
     Ad = torch.from_numpy(A).cuda()
     bd = torch.from_numpy(b).cuda()
     ctx = F.Context(0)
@@ -100,7 +120,9 @@ def main():
         return dt, prof, out
 
     dt_plain, prof_plain, (x_plain, _, S_plain) = timed(False, args.steps)
+    progress(f"timed {args.steps} plain steps: {dt_plain * 1e3:.3f} ms/step")
     dt_bf16, prof_bf16, (x_bf16, _, S_bf16) = timed(True, args.steps)
+    progress(f"timed {args.steps} bf16 steps: {dt_bf16 * 1e3:.3f} ms/step")
 
     pass1_bytes = w.n * q * 4
     pass2_bytes = w.n * q * 4 + w.n * 4
@@ -120,7 +142,23 @@ def main():
                               iters=120)
         ref = F.fct_l1_objective(ctx, Ad, bd, x_ref)
 
-    cpu = None if args.skip_cpu else cpu_oracle_sample(A, b, w, args.cpu_rows)
+    if args.profile_copy_mib > 0:
+        src = torch.empty(args.profile_copy_mib << 18, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    from paper_1207_4684_amd.profile_summary import source_sha256
+    traffic = committed_traffic(source_sha256(), os.path.join(
+        ROOT, "profiles", "pmc_pass1_wave_kernel_tall-4194304x32-f32.txt"))
+
+    if not args.skip_cpu:
+        progress("timing the CPU oracle")
+    cpu = None if args.skip_cpu else cpu_oracle_run(A, b, w, args.cpu_rows)
 
     rec = {
         "metric": METRIC,
@@ -138,8 +176,10 @@ def main():
         "config": {"workload": w.name, "n": w.n, "d": w.d, "s": w.s, "r1": w.r1, "r2": w.r2,
                    "s_out": w.s_out, "eps": w.eps, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(p1_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(p1_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "pass1_kernel (FCT1 sketch)", "kernel_ms": round(p1_ms, 5)},
+                     "unit": "GB/s", "frac": round(p1_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": "pass1_wave_kernel (FCT1 sketch)", "kernel_ms": round(p1_ms, 5),
+                     "algorithmic_bytes": pass1_bytes},
         "cpu_baseline": cpu,
         "passes": {
             "pass1_ms": round(p1_ms, 5), "pass1_GBps": round(p1_gbs, 1),

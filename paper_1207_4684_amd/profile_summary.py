@@ -1,0 +1,135 @@
+"""Text summaries of rocprofv3 result databases (rocpd SQLite files).
+
+    python -m paper_1207_4684_amd.profile_summary stats DB [--match SUBSTR]
+    python -m paper_1207_4684_amd.profile_summary traffic FETCH_DB WRITE_DB \
+        --kernel SUBSTR --copy-bytes N --algorithmic-bytes B
+
+``stats`` prints calls, total, average, minimum and maximum device time per
+kernel from the kernel trace.  ``traffic`` reads one database collected with
+``--pmc FETCH_SIZE`` and one with ``--pmc WRITE_SIZE`` (KiB per dispatch),
+scales each by what the same counter reads for the largest dispatch of the
+copy kernel (``--copy-kernel``, a copy of ``--copy-bytes`` bytes reads and
+writes that many bytes) in the same run, and prints the HBM bytes per launch of the kernel
+whose name contains ``--kernel``, with the SHA-256 of the sources that build
+it so a reader can tell whether the figures still describe the current code.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PASS1_SOURCES = ("csrc/pass1_wave.hip", "csrc/fct_device.h")
+
+
+def source_sha256(files=PASS1_SOURCES) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_stats(db: str, match: str | None = None):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, end - start from kernels").fetchall()
+    con.close()
+    agg: dict[str, list[float]] = {}
+    for name, dur in rows:
+        if match and match not in name:
+            continue
+        agg.setdefault(name, []).append(float(dur))
+    out = []
+    for name, d in agg.items():
+        out.append((name, len(d), sum(d) / 1e6, sum(d) / len(d) / 1e3, min(d) / 1e3, max(d) / 1e3))
+    out.sort(key=lambda r: -r[2])
+    return out
+
+
+def counter_per_dispatch(db: str, counter: str):
+    """(kernel name, mean counter value per dispatch, dispatches) per kernel."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select kernel_name, dispatch_id, sum(value) from counters_collection "
+        "where counter_name = ? group by kernel_name, dispatch_id", (counter,)).fetchall()
+    con.close()
+    agg: dict[str, list[float]] = {}
+    for name, _, v in rows:
+        agg.setdefault(name, []).append(float(v))
+    return {k: (sum(v) / len(v), len(v), max(v)) for k, v in agg.items()}
+
+
+def _short(name: str, width: int = 90) -> str:
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def cmd_stats(args):
+    print(f"# kernel trace summary of {os.path.basename(args.db)}")
+    print(f"{'kernel':90s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}")
+    for name, n, tot, avg, mn, mx in kernel_stats(args.db, args.match):
+        print(f"{_short(name):90s} {n:6d} {tot:10.3f} {avg:10.2f} {mn:10.2f} {mx:10.2f}")
+
+
+def _copy_value(table, pattern):
+    cands = [(mx, v, n, k) for k, (v, n, mx) in table.items() if pattern in k.lower()]
+    if not cands:
+        raise SystemExit("no copy kernel in the counter database")
+    mx, v, n, k = max(cands)
+    return mx, k
+
+
+def cmd_traffic(args):
+    fetch = counter_per_dispatch(args.fetch_db, "FETCH_SIZE")
+    write = counter_per_dispatch(args.write_db, "WRITE_SIZE")
+    fk = [k for k in fetch if args.kernel in k]
+    wk = [k for k in write if args.kernel in k]
+    if not fk or not wk:
+        raise SystemExit(f"kernel {args.kernel!r} not found in the counter databases")
+    f_val, f_n, _ = fetch[fk[0]]
+    w_val, w_n, _ = write[wk[0]]
+    cf, cf_name = _copy_value(fetch, args.copy_kernel.lower())
+    cw, cw_name = _copy_value(write, args.copy_kernel.lower())
+    f_scale = args.copy_bytes / (cf * 1024.0)
+    w_scale = args.copy_bytes / (cw * 1024.0)
+    hbm = f_val * 1024.0 * f_scale + w_val * 1024.0 * w_scale
+    print(f"kernel: {fk[0]}")
+    print(f"dispatches_fetch: {f_n}")
+    print(f"dispatches_write: {w_n}")
+    print(f"fetch_kib_per_dispatch: {f_val:.1f}")
+    print(f"write_kib_per_dispatch: {w_val:.1f}")
+    print(f"copy_kernel: {cf_name}")
+    print(f"copy_bytes: {args.copy_bytes}")
+    print(f"copy_fetch_kib: {cf:.1f}")
+    print(f"copy_write_kib: {cw:.1f}")
+    print(f"fetch_scale: {f_scale:.4f}")
+    print(f"write_scale: {w_scale:.4f}")
+    print(f"hbm_bytes_per_launch: {hbm:.0f}")
+    if args.algorithmic_bytes:
+        print(f"algorithmic_bytes_per_launch: {args.algorithmic_bytes}")
+        print(f"traffic_over_algorithmic: {hbm / args.algorithmic_bytes:.4f}")
+    print(f"source_sha256: {source_sha256()}")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--match")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_db")
+    t.add_argument("write_db")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--algorithmic-bytes", type=int, default=0)
+    t.add_argument("--copy-kernel", default="copy",
+                   help="substring naming the copy kernel of known size")
+    args = ap.parse_args(argv)
+    {"stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
