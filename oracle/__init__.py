@@ -19,8 +19,8 @@ data-parallel path:
 * ``sampling`` -- lambda_i = median_j |(X R^-1 Pi2)_ij|, p_i, the Bernoulli
                   sampling matrix D and the gathered coreset (steps 4-7);
 * ``l1``       -- exact l1 optima (brute force over interpolating subsets,
-                  linear programming, a vertex certificate, weighted medians)
-                  and an IRLS solver for the coreset problem (step 8);
+                  linear programming as in step 8, a vertex certificate, a
+                  weak-duality lower bound, weighted medians);
 * ``pipeline`` -- the whole FastCauchyRegression path;
 * ``lowp``     -- round-to-nearest-even BF16 rounding with integer operations.
 
