@@ -63,7 +63,7 @@ hipError_t launch_qr(const double* Y, int r1, int q, double* work, double* R, do
 hipError_t launch_form_m(const double* R, int q, int r2, int ldm, uint64_t seed,
                          uint32_t instance, double* Md, float* Mf, float* Mfb, uint16_t* Mb,
                          int* status, hipStream_t st);
-int r2_padded(int r2);
+__host__ __device__ int r2_padded(int r2);
 
 // Pass 2: lambda and per-workgroup FP64 partial sums of lambda.
 struct Pass2Args {

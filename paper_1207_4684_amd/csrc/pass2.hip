@@ -57,6 +57,12 @@ __device__ __forceinline__ void bitonic_sort(TA (&v)[N]) {
   }
 }
 
+__host__ __device__ int r2_padded(int r2) {
+  int p = 4;
+  while (p < r2) p <<= 1;
+  return p;
+}
+
 template <typename TA>
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -104,8 +110,195 @@ __global__ void __launch_bounds__(kP2Threads) pass2_valu_kernel(Pass2Args a) {
   if (threadIdx.x == 0) a.wg_sums[blockIdx.x] = s;
 }
 
+// MFMA form for FP32 and BF16 data.  Lambda^T = M^T X^T is formed on the
+// matrix cores: A = M^T (16 r2-columns x K) is constant and held in registers,
+// B = X^T (K x 16 rows) is loaded straight from the column-major X (16
+// consecutive rows of one column per 16 lanes), and D holds, in lane l,
+// register i, the value (row l % 16, r2-column 4 (l / 16) + i).  FP32 uses
+// v_mfma_f32_16x16x4f32 (K = 4 per instruction), BF16 uses
+// v_mfma_f32_16x16x16bf16_1k (K = 16, products exact, FP32 accumulation).
+// Each wave takes 64-row tiles; D goes through LDS so that lane l then owns
+// row l, takes |.|, sorts its r2 values and stores the median.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+template <int MT>
+__global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a) {
+  constexpr int R2P = 16 * MT, LS = R2P + 4;
+  __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS];
+  __shared__ double red[kP2Threads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r2p = r2_padded(a.r2);
+  const float* __restrict__ Mf = reinterpret_cast<const float*>(a.M);
+  const float* __restrict__ A = reinterpret_cast<const float*>(a.A);
+  const float* __restrict__ bv = reinterpret_cast<const float*>(a.b);
+  const int ks_n = (a.q + 3) >> 2;
+  // A operand: M[k][m], k = 4 ks + lane / 16, m = lane % 16 + 16 mt
+  float am[MT][17];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ks = 0; ks < 17; ++ks) {
+      const int k = 4 * ks + (lane >> 4), m = (lane & 15) + 16 * mt;
+      am[mt][ks] = (k < a.q && m < r2p) ? Mf[k * r2p + m] : 0.0f;
+    }
+  float* L = lds[wave];
+  double lsum = 0.0;
+  const int64_t ntiles = (a.n + 63) >> 6;
+  for (int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave; t < ntiles;
+       t += (int64_t)gridDim.x * (kP2Threads / 64)) {
+    const int64_t r0 = t << 6;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t row = r0 + 16 * nt + (lane & 15);
+      const bool rin = row < a.n;
+      float xb[17];
+#pragma unroll
+      for (int ks = 0; ks < 17; ++ks) {
+        const int c = 4 * ks + (lane >> 4);
+        float v = 0.0f;
+        if (ks < ks_n && rin && c < a.q) v = c < a.d ? A[row + (int64_t)c * a.lda] : -bv[row];
+        xb[ks] = v;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 17; ++ks)
+          if (ks < ks_n) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[mt][ks], xb[ks], acc, 0, 0, 0);
+        *reinterpret_cast<f32x4*>(L + (16 * nt + (lane & 15)) * LS + 16 * mt + 4 * (lane >> 4)) = acc;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float v[R2P];
+#pragma unroll
+    for (int j = 0; j < R2P; j += 4) {
+      const f32x4 q4 = *reinterpret_cast<const f32x4*>(L + lane * LS + j);
+      v[j] = q4[0];
+      v[j + 1] = q4[1];
+      v[j + 2] = q4[2];
+      v[j + 3] = q4[3];
+    }
+#pragma unroll
+    for (int j = 0; j < R2P; ++j) v[j] = j < a.r2 ? fabsf(v[j]) : INFINITY;
+    bitonic_sort<float, R2P>(v);
+    const int k1 = (a.r2 - 1) >> 1, k2 = a.r2 >> 1;
+    float m1 = v[0], m2 = v[0];
+#pragma unroll
+    for (int j = 1; j < R2P; ++j) {
+      m1 = (j == k1) ? v[j] : m1;
+      m2 = (j == k2) ? v[j] : m2;
+    }
+    const float lam = 0.5f * (m1 + m2);
+    const int64_t row = r0 + lane;
+    if (row < a.n) {
+      a.lambda[row] = lam;
+      lsum += (double)lam;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const double s = block_sum<double>(lsum, red);
+  if (threadIdx.x == 0) a.wg_sums[blockIdx.x] = s;
+}
+
+template <int MT>
+__global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a) {
+  constexpr int R2P = 16 * MT, LS = R2P + 4;
+  __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS];
+  __shared__ double red[kP2Threads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r2p = r2_padded(a.r2);
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(a.A);
+  const uint16_t* __restrict__ bv = reinterpret_cast<const uint16_t*>(a.b);
+  const int ks_n = (a.q + 15) >> 4;
+  // A operand: M[k][m] as BF16, k = 16 ks + 4 (lane / 16) + j, m = lane % 16 + 16 mt
+  s16x4 am[MT][5];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ks = 0; ks < 5; ++ks)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * ks + 4 * (lane >> 4) + j, m = (lane & 15) + 16 * mt;
+        am[mt][ks][j] = (k < a.q && m < r2p) ? (short)a.Mb[k * r2p + m] : (short)0;
+      }
+  float* L = lds[wave];
+  double lsum = 0.0;
+  const int64_t ntiles = (a.n + 63) >> 6;
+  for (int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave; t < ntiles;
+       t += (int64_t)gridDim.x * (kP2Threads / 64)) {
+    const int64_t r0 = t << 6;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t row = r0 + 16 * nt + (lane & 15);
+      const bool rin = row < a.n;
+      s16x4 xb[5];
+#pragma unroll
+      for (int ks = 0; ks < 5; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = 16 * ks + 4 * (lane >> 4) + j;
+          uint16_t v = 0;
+          if (ks < ks_n && rin && c < a.q)
+            v = c < a.d ? A[row + (int64_t)c * a.lda] : (uint16_t)(bv[row] ^ 0x8000u);
+          xb[ks][j] = (short)v;
+        }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 5; ++ks)
+          if (ks < ks_n) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[mt][ks], xb[ks], acc, 0, 0, 0);
+        *reinterpret_cast<f32x4*>(L + (16 * nt + (lane & 15)) * LS + 16 * mt + 4 * (lane >> 4)) = acc;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float v[R2P];
+#pragma unroll
+    for (int j = 0; j < R2P; j += 4) {
+      const f32x4 q4 = *reinterpret_cast<const f32x4*>(L + lane * LS + j);
+      v[j] = q4[0];
+      v[j + 1] = q4[1];
+      v[j + 2] = q4[2];
+      v[j + 3] = q4[3];
+    }
+#pragma unroll
+    for (int j = 0; j < R2P; ++j) v[j] = j < a.r2 ? fabsf(v[j]) : INFINITY;
+    bitonic_sort<float, R2P>(v);
+    const int k1 = (a.r2 - 1) >> 1, k2 = a.r2 >> 1;
+    float m1 = v[0], m2 = v[0];
+#pragma unroll
+    for (int j = 1; j < R2P; ++j) {
+      m1 = (j == k1) ? v[j] : m1;
+      m2 = (j == k2) ? v[j] : m2;
+    }
+    const float lam = 0.5f * (m1 + m2);
+    const int64_t row = r0 + lane;
+    if (row < a.n) {
+      a.lambda[row] = lam;
+      lsum += (double)lam;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const double s = block_sum<double>(lsum, red);
+  if (threadIdx.x == 0) a.wg_sums[blockIdx.x] = s;
+}
+
 int pass2_grid(int64_t n, int kind) {
-  (void)kind;
+  if (kind != kPass2F64) {
+    // MFMA forms: 64-row tiles per wave, about four workgroups per CU
+    int64_t want = (n + 255) / 256;
+    if (want > 1024) want = 1024;
+    return (int)(want < 1 ? 1 : want);
+  }
   int64_t want = (n + kP2Threads - 1) / kP2Threads;
   if (want > 2048) want = 2048;
   return (int)(want < 1 ? 1 : want);
@@ -124,17 +317,20 @@ static hipError_t launch_pass2_t(const Pass2Args& a, int r2p, hipStream_t st) {
   return hipGetLastError();
 }
 
-int r2_padded(int r2) {
-  int p = 4;
-  while (p < r2) p <<= 1;
-  return p;
-}
 
 hipError_t launch_pass2(const Pass2Args& a, int kind, hipStream_t st) {
   const int r2p = r2_padded(a.r2);
   if (kind == kPass2F64) return launch_pass2_t<double>(a, r2p, st);
-  if (kind == kPass2BF16) return launch_pass2_t<Bf16>(a, r2p, st);
-  return launch_pass2_t<float>(a, r2p, st);
+  if (a.q > 65 || a.r2 > 32) return hipErrorInvalidValue;
+  const int grid = pass2_grid(a.n, kind);
+  if (kind == kPass2BF16) {
+    if (r2p <= 16) hipLaunchKernelGGL((pass2_mfma_bf16_kernel<1>), dim3(grid), dim3(kP2Threads), 0, st, a);
+    else hipLaunchKernelGGL((pass2_mfma_bf16_kernel<2>), dim3(grid), dim3(kP2Threads), 0, st, a);
+  } else {
+    if (r2p <= 16) hipLaunchKernelGGL((pass2_mfma_f32_kernel<1>), dim3(grid), dim3(kP2Threads), 0, st, a);
+    else hipLaunchKernelGGL((pass2_mfma_f32_kernel<2>), dim3(grid), dim3(kP2Threads), 0, st, a);
+  }
+  return hipGetLastError();
 }
 
 // out = sum of parts[0..count) in a fixed order (one workgroup).
