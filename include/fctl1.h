@@ -105,6 +105,24 @@ int fct_sketch(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda, f
                void *Y, double *R);
 
 /*
+ * fct_sketch_window: the share of Pi1 X contributed by rows
+ * [row0, row0 + n) of a larger design.  Pi1 acts block by block (FCT1
+ * section: H~ is block diagonal, and B and C act on stacked positions), so
+ * with every random stream indexed by the global row the sketches of
+ * consecutive windows add up to the sketch of their union.  This is how a
+ * design split across devices or streamed in pieces is sketched.
+ *   A, b: device pointers to the window's first row (element (row0 + i, j)
+ *         of the whole design at A[i + j * lda]); n rows in the window.
+ *   row0: global index of the window's first row; a multiple of s and of
+ *         256, else FCT_ERR_BAD_ARG.  The last window may end anywhere: rows
+ *         past its end count as zero padding of the whole design.
+ *   Other arguments and Y as in fct_sketch (no R: a window has no basis).
+ */
+int fct_sketch_window(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda,
+                      fct_dtype dt, const void *b, int32_t s, int32_t r1, uint64_t seed,
+                      int64_t row0, uint32_t flags, void *Y);
+
+/*
  * l1_sample_probs: steps 3-6 of the regression figure.
  *   M = R^-1 Pi2 (q x r2, Pi2 of independent Cauchys from the seed) is formed
  *   on the device in FP64, then X is streamed once:

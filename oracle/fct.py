@@ -65,7 +65,8 @@ def padded_rows(n: int, s: int) -> int:
 
 
 def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
-              instance: int = 0, cauchy_one: bool = False, return_scale: bool = False):
+              instance: int = 0, cauchy_one: bool = False, return_scale: bool = False,
+              row0: int = 0):
     """Y = Pi1 X in FP64 for X of shape (n, q).
 
     ``cauchy_one`` replaces every Cauchy by 1 (used by conservation pins).
@@ -75,7 +76,12 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
     I-half.  Rounding errors of any evaluation order are bounded relative to
     this scale (a reading of "relative to each output row's scale": |Y_ij|
     itself can cancel, and so can a single (H_s z)_t).
+    ``row0`` (a multiple of s) places X as rows [row0, row0 + n) of a larger
+    design: every random stream is indexed by the global row, so the results
+    of consecutive windows add up to Pi1 of their union.
     """
+    if row0 % s:
+        raise ValueError("row0 must be a multiple of s")
     X = np.asarray(X, dtype=np.float64)
     n, q = X.shape
     n_pad = padded_rows(n, s)
@@ -83,9 +89,9 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
     z = np.zeros((n_pad, q))
     z[:n] = X
     if sign_flip:
-        z *= philox.signs(seed, n_pad, instance)[:, None]
+        z *= philox.signs(seed, n_pad, instance, row0)[:, None]
     hz = fwht_blocks(z.reshape(nb, s, q)).reshape(n_pad, q)
-    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, s, instance)
+    hH, cH, hI, cI = philox.pi1_streams(seed, n_pad, r1, s, instance, row0)
     if cauchy_one:
         cH = np.ones_like(cH)
         cI = np.ones_like(cI)

@@ -113,7 +113,8 @@ def certify_vertex(A, b, x_start, w=None, tol: float = 1e-9):
     return xv, objective(A, b, xv, w), optimal, lower
 
 
-def dual_lower_bound(A, b, x, w=None):
+def dual_lower_bound(A, b, x, w=None, rank_taus_only: bool = False, chunk: int = 1 << 20,
+                     threads: int = 1, max_free: int | None = None, stop_at: float | None = None):
     """A certified lower bound on min_x sum_i w_i |A_i x - b_i| (weak LP duality).
 
     For any y with A^T y = 0 and |y_i| <= w_i, and any x,
@@ -126,32 +127,97 @@ def dual_lower_bound(A, b, x, w=None):
     F is the basis and this is the classical certificate.  Several tau are
     tried; the best bound is returned.  Valid whatever produced x (up to the
     rounding of A^T y = 0); tight when x is optimal.
+
+    Products with A are formed in FP64 over row chunks (optionally on several
+    threads), so A may be a large FP32 array.  ``rank_taus_only`` tries only
+    the tau placed just above the d-th, (d+1)-th, 2d-th and 4d-th smallest
+    |r_i| (small free sets; enough when x is exactly at a vertex).
+    ``max_free`` skips tau whose free set has more rows; ``stop_at`` ends the
+    search once a bound reaches it, trying first the tau nearest (in ratio)
+    to the one just above the d smallest residuals.
     """
-    A = np.asarray(A, dtype=np.float64)
+    from concurrent.futures import ThreadPoolExecutor
+
     b = np.asarray(b, dtype=np.float64)
     n, d = A.shape
     w = np.ones(n) if w is None else np.asarray(w, dtype=np.float64)
-    r = A @ np.asarray(x, dtype=np.float64) - b
-    ar = np.sort(np.abs(r))
-    scale_r = float(ar[-1]) or 1.0
-    ranks = [ar[min(n - 1, k)] * 1.0001 for k in (d - 1, d, 2 * d, 4 * d)]
-    taus = sorted(set(np.concatenate([scale_r * 10.0 ** np.arange(-16.0, 0.5, 0.5), ranks])))
+    x = np.asarray(x, dtype=np.float64)
+    starts = list(range(0, n, chunk))
+
+    def rows(lo):
+        return np.asarray(A[lo:min(n, lo + chunk)], dtype=np.float64)
+
+    def pmap(fn):
+        if threads > 1 and len(starts) > 1:
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                return list(ex.map(fn, starts))
+        return [fn(lo) for lo in starts]
+
+    def pmap_list(items, fn):
+        if threads > 1 and len(items) > 1:
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                return list(ex.map(fn, items))
+        return [fn(it) for it in items]
+
+    def matvec(v):
+        return np.concatenate(pmap(lambda lo: rows(lo) @ v))
+
+    def rmatvec(y, absolute=False):
+        if absolute:
+            parts = pmap(lambda lo: np.abs(rows(lo)).T @ np.abs(y[lo:lo + chunk]))
+        else:
+            parts = pmap(lambda lo: rows(lo).T @ y[lo:lo + chunk])
+        return np.sum(parts, axis=0)
+
+    r = matvec(x) - b
+    absr = np.abs(r)
+    ks = sorted({min(n - 1, k) for k in (d - 1, d, 2 * d, 4 * d)})
+    part = np.partition(absr, ks)
+    ranks = [part[k] * 1.0001 for k in ks]
+    scale_r = float(absr.max()) or 1.0
+    if rank_taus_only:
+        taus = sorted(set(ranks))
+    else:
+        taus = sorted(set(np.concatenate([scale_r * 10.0 ** np.arange(-16.0, 0.5, 0.5), ranks])))
+    if stop_at is not None:
+        ref = max(ranks[min(1, len(ranks) - 1)], 1e-300)
+        taus = sorted(taus, key=lambda t: abs(np.log(max(t, 1e-300) / ref)))
+    absAw = rmatvec(w, absolute=True).max()   # |A|^T |y| <= |A|^T w for |y| <= w
     best = -np.inf
     for tau in taus:
         if not tau > 0:
             continue
         y = w * np.clip(r / tau, -1.0, 1.0)
-        free = np.abs(r) < tau
-        if free.sum() < d:
+        free = absr < tau
+        nf = int(free.sum())
+        if nf < d or (rank_taus_only and nf > 64 * d) or (max_free is not None and nf > max_free):
             continue
-        AF = A[free]
-        g = A.T @ y
-        delta, *_ = np.linalg.lstsq(AF.T, -g, rcond=None)
-        y[free] += delta
-        if np.linalg.norm(A.T @ y) > 1e-9 * (np.abs(A).T @ np.abs(y)).max():
-            continue
+        fidx = np.flatnonzero(free)
+        g = rmatvec(y)
+        if nf <= (1 << 16):
+            AF = np.asarray(A[fidx], dtype=np.float64)
+            delta, *_ = np.linalg.lstsq(AF.T, -g, rcond=None)
+            res = g + AF.T @ delta
+        else:
+            # minimum-norm correction delta = A_F z with (A_F^T A_F) z = -g,
+            # solved after equilibrating the columns; formed over row chunks
+            fch = [fidx[i:i + chunk] for i in range(0, nf, chunk)]
+            K = np.sum(pmap_list(fch, lambda ix: (lambda B: B.T @ B)(np.asarray(A[ix], dtype=np.float64))),
+                       axis=0)
+            sc_c = 1.0 / np.sqrt(np.maximum(np.diag(K), 1e-300))
+            z = sc_c * np.linalg.solve(K * np.outer(sc_c, sc_c), -g * sc_c)
+            delta = np.concatenate(pmap_list(fch, lambda ix: np.asarray(A[ix], dtype=np.float64) @ z))
+            res = g + np.sum(pmap_list([np.arange(i, min(nf, i + chunk)) for i in range(0, nf, chunk)],
+                                       lambda ii: np.asarray(A[fidx[ii]], dtype=np.float64).T @ delta[ii]),
+                             axis=0)
+        y[fidx] += delta
         sc = max(1.0, float(np.max(np.abs(y) / w)))
+        # A^T y after the correction is g + A_F^T delta (no further pass over A)
+        if np.linalg.norm(res) > 1e-9 * absAw * sc:
+            continue
         best = max(best, float(-(y / sc) @ b))
+        if stop_at is not None and best >= stop_at:
+            break
     return best
 
 

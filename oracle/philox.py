@@ -114,27 +114,30 @@ def position_streams(seed: int, k, r1: int, instance: int = 0):
             cauchy_from_word(np.where(odd, w3, w1)))
 
 
-def row_positions(n_pad: int, s: int):
-    """Stacked positions of the H-half and I-half copies of padded rows j < n_pad."""
-    j = np.arange(n_pad, dtype=np.int64)
+def row_positions(n_pad: int, s: int, row0: int = 0):
+    """Stacked positions of the H-half and I-half copies of padded rows
+    j in [row0, row0 + n_pad) (row0 a multiple of s)."""
+    j = np.arange(row0, row0 + n_pad, dtype=np.int64)
     kH = 2 * s * (j // s) + j % s
     return kH, kH + s
 
 
-def pi1_streams(seed: int, n_pad: int, r1: int, s: int, instance: int = 0):
-    """Per padded row j: (bucket_H, cauchy_H, bucket_I, cauchy_I) of stream 0."""
-    kH, kI = row_positions(n_pad, s)
+def pi1_streams(seed: int, n_pad: int, r1: int, s: int, instance: int = 0, row0: int = 0):
+    """Per padded row j in [row0, row0 + n_pad): (bucket_H, cauchy_H, bucket_I, cauchy_I)."""
+    kH, kI = row_positions(n_pad, s, row0)
     hH, cH = position_streams(seed, kH, r1, instance)
     hI, cI = position_streams(seed, kI, r1, instance)
     return hH, cH, hI, cI
 
 
-def signs(seed: int, n_pad: int, instance: int = 0):
-    """D(j) in {+1, -1} for padded rows j < n_pad (stream 1)."""
-    ncalls = (n_pad + 127) // 128
-    words = np.stack(stream_words(seed, STREAM_SIGN, np.arange(ncalls, dtype=np.uint64), instance), axis=1)
-    j = np.arange(n_pad, dtype=np.uint64)
-    word = words.reshape(-1)[(j >> np.uint64(5)).astype(np.int64)].astype(np.uint64)
+def signs(seed: int, n_pad: int, instance: int = 0, row0: int = 0):
+    """D(j) in {+1, -1} for padded rows j in [row0, row0 + n_pad) (stream 1)."""
+    c0 = row0 // 128
+    ncalls = (row0 + n_pad + 127) // 128 - c0
+    words = np.stack(stream_words(seed, STREAM_SIGN, np.arange(c0, c0 + ncalls, dtype=np.uint64),
+                                  instance), axis=1)
+    j = np.arange(row0, row0 + n_pad, dtype=np.uint64)
+    word = words.reshape(-1)[((j >> np.uint64(5)) - np.uint64(4 * c0)).astype(np.int64)].astype(np.uint64)
     bit = (word >> (j & np.uint64(31))) & np.uint64(1)
     return 1.0 - 2.0 * bit.astype(np.float64)
 

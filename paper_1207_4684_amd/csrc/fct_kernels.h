@@ -21,6 +21,7 @@ struct Pass1Args {
   uint64_t seed;
   uint32_t instance;
   int32_t sign_flip;
+  int64_t row0g;       // global index of local row 0 (random streams are indexed globally)
   void* partials;      // [nranges][q][r1] of the input type
 };
 

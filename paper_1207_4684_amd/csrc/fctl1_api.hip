@@ -212,7 +212,7 @@ void carve_sketch(C& cv, const Pass1Plan& p, int q, int r1, size_t es, bool want
 
 int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64_t lda,
                fct_dtype dt, const void* b, int32_t s, int32_t r1, uint64_t seed, uint32_t flags,
-               void* Y, double* R, double** Yd_out, const Pass1Plan& p) {
+               void* Y, double* R, double** Yd_out, const Pass1Plan& p, int64_t row0g = 0) {
   const int q = d + (b ? 1 : 0);
   const int64_t n_pad = (n + s - 1) / s * s;
   const size_t es = esize(dt);
@@ -234,6 +234,7 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.seed = seed;
   a.instance = 0;
   a.sign_flip = (flags & FCT_FLAG_NO_SIGN_FLIP) ? 0 : 1;
+  a.row0g = row0g;
   a.partials = partials;
   prof_begin(c, 0);
   if (p.kind == 1) {
@@ -477,6 +478,24 @@ int fct_sketch(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fct
   if ((st = ensure_scratch(c, m.off))) return st;
   Carve cv(c->scratch);
   return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, R, nullptr, p);
+}
+
+int fct_sketch_window(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda,
+                      fct_dtype dt, const void* b, int32_t s, int32_t r1, uint64_t seed,
+                      int64_t row0, uint32_t flags, void* Y) {
+  int st = check_sketch_args(c, A, n, d, lda, dt, b, s, r1, false);
+  if (st) return st;
+  if (!Y || row0 < 0 || row0 % s != 0 || row0 % 256 != 0) return FCT_ERR_BAD_ARG;
+  const int q = d + (b ? 1 : 0);
+  const int64_t n_pad = (n + s - 1) / s * s;
+  int perr = 0;
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  Measure m;
+  carve_sketch(m, p, q, r1, esize(dt), false);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, nullptr, nullptr, p, row0);
 }
 
 int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,

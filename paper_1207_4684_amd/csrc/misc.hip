@@ -7,15 +7,19 @@
 
 namespace fctl1 {
 
+// Grid-stride: the dispatch's work-item count is a 32-bit quantity, so the
+// grid is capped and each thread converts several elements.
 __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t count, uint16_t* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const uint32_t u = __float_as_uint(x[i]);
-  y[i] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = __float_as_uint(x[i]);
+    y[i] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  }
 }
 
 hipError_t launch_to_bf16(const float* x, int64_t count, uint16_t* y, hipStream_t st) {
-  const int64_t blocks = (count + 255) / 256;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, count, y);
   return hipGetLastError();
 }

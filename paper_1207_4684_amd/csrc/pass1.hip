@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(1024) pass1_kernel(Pass1Args a) {
     __syncthreads();  // previous chunk's tile reads and sign words are done
     if (a.sign_flip) {
       for (int k = threadIdx.x; k < chunk / 128; k += NT) {
-        const uint4 w = stream_words(a.seed, kStreamSign, (uint64_t)(cr >> 7) + k, a.instance);
+        const uint4 w = stream_words(a.seed, kStreamSign, (uint64_t)((a.row0g + cr) >> 7) + k,
+                                     a.instance);
         sgnw[4 * k + 0] = w.x;
         sgnw[4 * k + 1] = w.y;
         sgnw[4 * k + 2] = w.z;
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(1024) pass1_kernel(Pass1Args a) {
       const int t = threadIdx.x + r * NT;
       const int64_t j = cr + t;
       valid[r] = j < row1;
-      const uint64_t kH = h_position((uint64_t)j, a.log2s);
+      const uint64_t kH = h_position((uint64_t)(a.row0g + j), a.log2s);
       uint32_t bH, wH, bI, wI;
       position_words(a.seed, a.instance, kH, a.r1, &bH, &wH);
       position_words(a.seed, a.instance, kH + a.s, a.r1, &bI, &wI);

@@ -130,13 +130,14 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
     if (a.sign_flip && ((tile - w0) % kSignRows) == 0) {
       sign_base = tile;
       if (lane < kSignRows / 128) {
-        const uint4 sw = stream_words(a.seed, kStreamSign, (uint64_t)(tile >> 7) + lane, a.instance);
+        const uint4 sw = stream_words(a.seed, kStreamSign, (uint64_t)((a.row0g + tile) >> 7) + lane,
+                                      a.instance);
         *reinterpret_cast<uint4*>(&W.sgn[4 * lane]) = sw;
       }
     }
     {
       // RNG table for rows tile + 4 lane + {0,1,2,3}: positions come in pairs
-      const uint64_t j0 = (uint64_t)tile + 4 * lane;
+      const uint64_t j0 = (uint64_t)(a.row0g + tile) + 4 * lane;
       const uint64_t kA = h_position(j0, a.log2s), kB = h_position(j0 + 2, a.log2s);
       const uint4 wa = stream_words(a.seed, kStreamPi1, kA >> 1, a.instance);
       const uint4 wb = stream_words(a.seed, kStreamPi1, kB >> 1, a.instance);

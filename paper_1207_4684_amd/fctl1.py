@@ -50,6 +50,8 @@ def _load():
         "fct_sync": (ctypes.c_int, [P]),
         "fct_stream": (P, [P]),
         "fct_sketch": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, P, I32, I32, U64, U32, P, P]),
+        "fct_sketch_window": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, P, I32, I32, U64,
+                                             I64, U32, P]),
         "l1_sample_probs": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64, I64,
                                            P, P, P]),
         "l1_coreset": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64,
@@ -75,6 +77,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream", "fct_sketch",
+            "fct_sketch_window",
             "l1_sample_probs", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
             "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
             "fct_profile", "fct_profile_read")
@@ -165,6 +168,17 @@ def fct_sketch(ctx, A, b, s, r1, seed, flags=0, want_y=True, want_r=True):
     _check(_lib.fct_sketch(ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed, flags,
                            _ptr(Y), _ptr(R)), "fct_sketch")
     return (Y.t() if Y is not None else None), (R.t() if R is not None else None)
+
+
+def fct_sketch_window(ctx, A, b, s, r1, seed, row0, flags=0):
+    """The share of Pi1 X from a window of rows starting at global row ``row0``
+    (A, b are the window's rows); returns the r1 x q view."""
+    n, d, lda = _cm(A)
+    q = d + (1 if b is not None else 0)
+    Y = torch.empty((q, r1), dtype=A.dtype, device=A.device)
+    _check(_lib.fct_sketch_window(ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed,
+                                  int(row0), flags, _ptr(Y)), "fct_sketch_window")
+    return Y.t()
 
 
 def l1_sample_probs(ctx, A, b, R, r2, seed, s_out, want_p=True):

@@ -120,3 +120,20 @@ def test_row_scale_bounds_result():
     X = np.random.default_rng(5).standard_normal((500, 4))
     Y, S = fct.pi1_apply(X, 16, 20, seed=1, return_scale=True)
     assert np.all(np.abs(Y).max(axis=1) <= S * (1 + 1e-12))
+
+
+def test_row_windows_add_up_to_the_whole():
+    # Pi1 acts block by block and the streams are indexed by the global row, so
+    # the sketches of consecutive windows (global offsets) sum to the sketch of
+    # the whole design; each window equals the columns of dense Pi1 it touches.
+    n, s, r1 = 1000, 16, 24
+    X = np.random.default_rng(8).standard_normal((n, 3))
+    whole = fct.pi1_apply(X, s, r1, seed=5)
+    cuts = [0, 256, 512, 768, n]
+    parts = sum(fct.pi1_apply(X[a:b], s, r1, seed=5, row0=a) for a, b in zip(cuts[:-1], cuts[1:]))
+    assert np.allclose(parts, whole, rtol=1e-12, atol=1e-12 * np.abs(whole).max())
+    P = fct.pi1_dense(n, s, r1, seed=5)
+    assert np.allclose(fct.pi1_apply(X[256:512], s, r1, seed=5, row0=256), P[:, 256:512] @ X[256:512],
+                       rtol=1e-12, atol=1e-10)
+    with pytest.raises(ValueError):
+        fct.pi1_apply(X[:40], s, r1, seed=5, row0=8)

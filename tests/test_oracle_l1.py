@@ -100,3 +100,15 @@ def test_bf16_rounding_matches_torch():
     ours = lowp.f32_to_bf16_bits(x)
     ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     assert np.array_equal(ours, ref)
+
+
+def test_dual_lower_bound_chunked_rank_taus():
+    # the large-n mode (FP64 products over row chunks, tau only at the ranks
+    # just above the d smallest residuals) is still a valid and tight bound
+    g = np.random.default_rng(9)
+    A = (g.standard_normal((5000, 6)) * 10.0 ** g.uniform(-2, 2, 6)).astype(np.float32)
+    b = A.astype(np.float64) @ g.standard_normal(6) + g.laplace(size=5000)
+    xl, fl = l1.lp(A.astype(np.float64), b)
+    lb = l1.dual_lower_bound(A, b, xl, rank_taus_only=True, chunk=777)
+    assert lb <= fl * (1 + 1e-9) and lb >= fl * (1 - 1e-6)
+    assert l1.dual_lower_bound(A, b, np.zeros(6), rank_taus_only=True, chunk=777) <= fl * (1 + 1e-9)

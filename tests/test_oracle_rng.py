@@ -124,3 +124,11 @@ def test_streams_and_instances_independent():
     b = philox.stream_words(1, 1, np.arange(64))[0]
     c = philox.stream_words(1, 0, np.arange(64), instance=1)[0]
     assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_windowed_streams_are_slices_of_the_whole():
+    full = philox.pi1_streams(6, 4096, 50, 64)
+    win = philox.pi1_streams(6, 1024, 50, 64, row0=2048)
+    for a, b in zip(full, win):
+        assert np.array_equal(a[2048:3072], b)
+    assert np.array_equal(philox.signs(6, 4096)[1280:1280 + 700], philox.signs(6, 700, row0=1280))
