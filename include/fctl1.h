@@ -169,6 +169,50 @@ int l1_regress(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
                const fct_params *prm, double *x, double *obj, int64_t *S_out);
 
 /*
+ * One instance of a batch: the arguments of l1_regress for one design.
+ * prm.s == 0 asks the library to choose the FWHT block size (see below).
+ */
+typedef struct {
+  const void *A;       /* device, column-major n x d, leading dimension lda  */
+  const void *b;       /* device, length n                                    */
+  const void *A_lowp;  /* NULL, or the BF16 copy of A (then pass 2 reads it)  */
+  const void *b_lowp;  /* BF16 copy of b when A_lowp != NULL                  */
+  int64_t n;
+  int64_t lda;
+  int64_t ld_lowp;
+  int32_t d;           /* 1 <= d <= 64                                        */
+  int32_t pad0;
+  fct_params prm;      /* as for l1_regress; s == 0: autotuned                */
+} fct_instance;
+
+/*
+ * l1_regress_batched: the regression figure's steps 1-8 for `count`
+ * independent instances of uneven n and d, all of element type dt
+ * (FCT_F32 or FCT_F64).  No host synchronization happens inside the batch:
+ * the whole sequence (every instance's sketch, QR, row-norm pass, selection
+ * and gather, then one launch that solves all coresets, one workgroup per
+ * instance) is captured into a HIP graph on the context's stream (instances
+ * spread over four forked streams) and replayed on later calls with the same
+ * instances, sizes and scratch; if capture is refused the sequence runs
+ * eagerly.
+ * Autotuning: for instances with prm.s == 0 the library times pass 1 for
+ *   s in {64, 128, 256, 512} on the first instance of each (d, dt) class and
+ *   keeps the fastest in the context (s_used reports it).
+ * eps: default expected coreset size s_out = ceil(20 q / eps) when prm.s_out <= 0.
+ * Outputs (host): x[off_i .. off_i + d_i) with off_i = sum_{k<i} d_k;
+ *   obj, S, s_used, status: count entries each, any may be NULL except status.
+ *   status[i]: FCT_OK, FCT_ERR_CAPACITY (S_i > 2 s_out + 8 sqrt(s_out) + 1024;
+ *   x not valid), FCT_ERR_RANK_DEFICIENT (singular coreset system) or
+ *   FCT_ERR_HIP (the solver's wait timed out).
+ * Returns FCT_OK if every instance succeeded, else the first failing status
+ * (or a context-wide FCT_ERR_NONFINITE / FCT_ERR_RANK_DEFICIENT flagged by a
+ * sketch).
+ */
+int l1_regress_batched(fct_ctx *ctx, const fct_instance *inst, int32_t count, fct_dtype dt,
+                       double eps, double *x, double *obj, int64_t *S, int32_t *s_used,
+                       int32_t *status);
+
+/*
  * l1_select: steps 6-7 alone, from row-norm estimates already computed
  * (l1_sample_probs): p_i = min{1, s_out lambda_i / sum_lambda} in FP64 and
  * row i kept iff its stream-3 word is below floor(p_i 2^32).  Several draws

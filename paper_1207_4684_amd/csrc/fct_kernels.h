@@ -113,6 +113,29 @@ hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, c
 
 // Step 8: weighted l1 solve by FP64 IRLS.
 size_t irls_work_doubles(int64_t S, int d);
+// Arguments of one IRLS solve (step 8).
+struct IrlsArgs {
+  const void* At;
+  const void* bt;
+  const double* w;
+  const int64_t* S_dev;
+  int64_t cap;
+  int64_t ldat;
+  int d;
+  int iters;
+  int row_target;  // coreset rows per active workgroup
+  double* part;    // 2 x workgroups x pstride
+  unsigned* bar;   // [0] arrival counter (zero at launch), [1] abort flag
+  double* x_out;
+  double* obj_out;
+  int* status;
+};
+// Batched form: one workgroup per instance (all of one element type); work
+// of irls_batched_work_doubles(d) doubles per instance, barrier words at
+// irls_batched_bar(work, d); arr is a device array of count instances.
+size_t irls_batched_work_doubles(int d);
+unsigned* irls_batched_bar(double* work, int d);
+hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStream_t st);
 // Persistent cooperative IRLS: S_hint (host) sizes the grid, the device count
 // S_dev (clamped to cap) is the number of rows; x_out[d], obj_out[1].
 hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <vector>
 
 #include "../../include/fctl1.h"
 #include "fct_kernels.h"
@@ -33,6 +35,15 @@ struct fct_ctx {
   size_t p1_lds_budget = 0;     // 0: the device's opt-in maximum
   int p1_waves_of_wgs = 1;
   int p1_force_tile = 0;        // 1: never use the wave-level pass-1 kernel
+  // batched form: forked streams, events, staging and the cached graph
+  static constexpr int kBranches = 4;
+  hipStream_t branch[kBranches] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kBranches] = {};
+  void* bpinned = nullptr;
+  size_t bpinned_bytes = 0;
+  hipGraphExec_t bgraph = nullptr;
+  std::vector<char> bsig;       // signature of the captured batch
+  std::map<int, int> tuned_s;   // (d << 1 | f64) -> FWHT block size
 };
 
 namespace {
@@ -86,6 +97,11 @@ struct Measure {
 int ensure_scratch(fct_ctx* c, size_t bytes) {
   if (bytes <= c->scratch_bytes) return FCT_OK;
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->bgraph) {  // a captured batch points into the old arena
+    (void)hipGraphExecDestroy(c->bgraph);
+    c->bgraph = nullptr;
+    c->bsig.clear();
+  }
   if (c->scratch) HIP_TRY(hipFree(c->scratch));
   c->scratch = nullptr;
   c->scratch_bytes = 0;
@@ -405,6 +421,13 @@ void fct_destroy(fct_ctx* c) {
     for (int i = 0; i < 2 * fct_ctx::kProfSlots; ++i) (void)hipEventDestroy(c->prof_ev[k][i]);
     delete[] c->prof_ev[k];
   }
+  if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
+  for (int k = 0; k < fct_ctx::kBranches; ++k) {
+    if (c->branch[k]) (void)hipStreamDestroy(c->branch[k]);
+    if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->bpinned) (void)hipHostFree(c->bpinned);
   if (c->scratch) (void)hipFree(c->scratch);
   if (c->flags) (void)hipFree(c->flags);
   if (c->pinned) (void)hipHostFree(c->pinned);
@@ -734,6 +757,312 @@ int l1_regress(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, i
     return FCT_OK;
   }
   return FCT_ERR_CAPACITY;
+}
+
+
+// ---- batched form ----------------------------------------------------------
+
+namespace {
+
+__global__ void batch_collect_kernel(const IrlsArgs* __restrict__ arr, int count,
+                                     double* __restrict__ out) {
+  // out row i: [0, 64) x, [64] objective, [65] S, [66] solver status
+  const int i = blockIdx.x;
+  if (i >= count) return;
+  const IrlsArgs a = arr[i];
+  for (int k = threadIdx.x; k < a.d; k += blockDim.x) out[i * 72 + k] = a.x_out[k];
+  if (threadIdx.x == 0) {
+    out[i * 72 + 64] = *a.obj_out;
+    out[i * 72 + 65] = (double)*a.S_dev;
+    out[i * 72 + 66] = (double)*a.status;
+  }
+}
+
+struct BatchItem {
+  fct_params prm;
+  int64_t cap;
+  size_t off;     // byte offset of the instance's region in the scratch arena
+  size_t bytes;
+};
+
+int batch_ensure_aux(fct_ctx* c, size_t pinned_bytes) {
+  if (!c->branch[0]) {
+    for (int k = 0; k < fct_ctx::kBranches; ++k) {
+      HIP_TRY(hipStreamCreateWithFlags(&c->branch[k], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  }
+  if (c->bpinned_bytes < pinned_bytes) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->bpinned) HIP_TRY(hipHostFree(c->bpinned));
+    c->bpinned = nullptr;
+    c->bpinned_bytes = 0;
+    HIP_TRY(hipHostMalloc(&c->bpinned, pinned_bytes, hipHostMallocDefault));
+    c->bpinned_bytes = pinned_bytes;
+  }
+  return FCT_OK;
+}
+
+// Pass-1 time (ms) of one sketch of instance `in` with block size s.
+int time_sketch(fct_ctx* c, const fct_instance& in, fct_dtype dt, int s, float* ms) {
+  const int q = in.d + 1;
+  const int64_t n_pad = (in.n + s - 1) / s * s;
+  int perr = 0;
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, in.prm.r1, esize(dt), &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  Measure m;
+  carve_sketch(m, p, q, in.prm.r1, esize(dt), false);
+  int st;
+  if ((st = ensure_scratch(c, m.off))) return st;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (int rep = 0; rep < 3; ++rep) {
+    Carve cv(c->scratch);
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    if ((st = run_sketch(c, cv, in.A, in.n, in.d, in.lda, dt, in.b, s, in.prm.r1, in.prm.seed,
+                         in.prm.flags, nullptr, nullptr, nullptr, p)))
+      return st;
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    if (rep > 0 && t < best) best = t;  // the first run warms up
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return FCT_OK;
+}
+
+// Every instance's steps 1-7 on the forked streams, then the batched solve
+// and the collection of outputs on the context stream.
+int batch_enqueue(fct_ctx* c, const fct_instance* inst, int count, fct_dtype dt,
+                  const std::vector<BatchItem>& items, const IrlsArgs* args_dev, double* out_dev,
+                  size_t out_bytes) {
+  const size_t es = esize(dt);
+  HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+  for (int k = 0; k < fct_ctx::kBranches; ++k) HIP_TRY(hipStreamWaitEvent(c->branch[k], c->ev_fork, 0));
+  hipStream_t main = c->stream;
+  int st = FCT_OK;
+  for (int i = 0; i < count && st == FCT_OK; ++i) {
+    const fct_instance& in = inst[i];
+    const BatchItem& it = items[i];
+    const int d = in.d;
+    Carve cv(c->scratch);
+    cv.off = it.off;
+    int64_t* S_dev = cv.take<int64_t>(1);
+    char* At = cv.take<char>((size_t)it.cap * d * es);
+    char* bt = cv.take<char>((size_t)it.cap * es);
+    double* w = cv.take<double>((size_t)it.cap);
+    int64_t* idx = cv.take<int64_t>((size_t)it.cap);
+    cv.take<double>(irls_batched_work_doubles(d));
+    cv.take<double>(72);
+    cv.take<int>(4);
+    Carve rest(c->scratch);
+    rest.off = cv.off;
+    c->stream = c->branch[i % fct_ctx::kBranches];
+    st = coreset_impl(c, in.A, in.b, in.n, d, in.lda, dt, in.A_lowp, in.b_lowp, in.ld_lowp, &it.prm,
+                      it.cap, At, bt, w, idx, S_dev, rest);
+    c->stream = main;
+  }
+  if (st) return st;
+  for (int k = 0; k < fct_ctx::kBranches; ++k) {
+    HIP_TRY(hipEventRecord(c->ev_join[k], c->branch[k]));
+    HIP_TRY(hipStreamWaitEvent(main, c->ev_join[k], 0));
+  }
+  HIP_TRY(launch_irls_batched(args_dev, count, dt == FCT_F64, main));
+  hipLaunchKernelGGL(batch_collect_kernel, dim3(count), dim3(64), 0, main, args_dev, count, out_dev);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->bpinned, out_dev, out_bytes, hipMemcpyDeviceToHost, main));
+  return FCT_OK;
+}
+
+}  // namespace
+
+int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_dtype dt,
+                       double eps, double* x, double* obj, int64_t* S, int32_t* s_used,
+                       int32_t* status) {
+  if (!c || !inst || count < 1 || !x || !status) return FCT_ERR_BAD_ARG;
+  if (dt != FCT_F32 && dt != FCT_F64) return FCT_ERR_BAD_ARG;
+  struct ProfOff {  // no timing events inside a batch (they would be captured)
+    fct_ctx* c;
+    bool saved;
+    explicit ProfOff(fct_ctx* cc) : c(cc), saved(cc->prof_on) { c->prof_on = false; }
+    ~ProfOff() { c->prof_on = saved; }
+  } prof_off(c);
+  int st;
+  std::vector<BatchItem> items((size_t)count);
+  const size_t es = esize(dt);
+  // arguments, autotuning, sizes
+  for (int i = 0; i < count; ++i) {
+    const fct_instance& in = inst[i];
+    if ((st = check_common(c, in.A, in.n, in.d, in.lda))) return st;
+    if (!in.b || in.d > 64) return FCT_ERR_BAD_ARG;
+    if (in.A_lowp && (!in.b_lowp || in.ld_lowp < in.n || dt != FCT_F32)) return FCT_ERR_BAD_ARG;
+    fct_params prm = in.prm;
+    if (prm.s_out <= 0) {
+      if (!(eps > 0.0)) return FCT_ERR_BAD_ARG;
+      prm.s_out = (int64_t)std::ceil(20.0 * (in.d + 1) / eps);
+    }
+    if (prm.irls_iters <= 0) prm.irls_iters = 80;
+    items[i].prm = prm;
+  }
+  for (int i = 0; i < count; ++i) {
+    fct_params& prm = items[i].prm;
+    if (prm.s != 0) continue;
+    const int key = (inst[i].d << 1) | (dt == FCT_F64 ? 1 : 0);
+    auto hit = c->tuned_s.find(key);
+    if (hit == c->tuned_s.end()) {
+      int best_s = 256;
+      float best_t = 1e30f;
+      for (int s : {64, 128, 256, 512}) {
+        fct_params trial = prm;
+        trial.s = s;
+        if (check_params(&trial, inst[i].d + 1)) continue;
+        fct_instance probe = inst[i];
+        probe.prm = trial;
+        float t = 0.0f;
+        if ((st = time_sketch(c, probe, dt, s, &t))) return st;
+        if (t < best_t) {
+          best_t = t;
+          best_s = s;
+        }
+      }
+      hit = c->tuned_s.emplace(key, best_s).first;
+    }
+    prm.s = hit->second;
+  }
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    fct_params& prm = items[i].prm;
+    if ((st = check_params(&prm, inst[i].d + 1))) return st;
+    const int d = inst[i].d;
+    int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
+    if (cap > inst[i].n) cap = inst[i].n;
+    items[i].cap = cap;
+    Measure m;
+    m.take<int64_t>(1);
+    m.take<char>((size_t)cap * d * es);
+    m.take<char>((size_t)cap * es);
+    m.take<double>((size_t)cap);
+    m.take<int64_t>((size_t)cap);
+    m.take<double>(irls_batched_work_doubles(d));
+    m.take<double>(72);
+    m.take<int>(4);
+    const size_t bytes = m.off + coreset_scratch(c, inst[i].n, d, dt, &prm, inst[i].A_lowp != nullptr) + 512;
+    items[i].off = total;
+    items[i].bytes = bytes;
+    total += (bytes + 255) & ~size_t(255);
+  }
+  const size_t args_off = total;
+  total += ((size_t)count * sizeof(IrlsArgs) + 255) & ~size_t(255);
+  const size_t out_off = total;
+  const size_t out_bytes = (size_t)count * 72 * sizeof(double);
+  total += out_bytes + 256;
+  if ((st = ensure_scratch(c, total))) return st;
+  const size_t pin_bytes = (size_t)count * sizeof(IrlsArgs) > out_bytes ? (size_t)count * sizeof(IrlsArgs) : out_bytes;
+  if ((st = batch_ensure_aux(c, pin_bytes))) return st;
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(c->scratch + args_off);
+  double* out_dev = reinterpret_cast<double*>(c->scratch + out_off);
+  // per-instance solver arguments (pointers into each instance's region)
+  std::vector<IrlsArgs> args((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    const int d = inst[i].d;
+    Carve cv(c->scratch);
+    cv.off = items[i].off;
+    IrlsArgs& a = args[i];
+    a.S_dev = cv.take<int64_t>(1);
+    a.At = cv.take<char>((size_t)items[i].cap * d * es);
+    a.bt = cv.take<char>((size_t)items[i].cap * es);
+    a.w = cv.take<double>((size_t)items[i].cap);
+    cv.take<int64_t>((size_t)items[i].cap);
+    double* work = cv.take<double>(irls_batched_work_doubles(d));
+    double* outv = cv.take<double>(72);
+    a.status = cv.take<int>(4);
+    a.cap = items[i].cap;
+    a.ldat = items[i].cap;
+    a.d = d;
+    a.iters = items[i].prm.irls_iters;
+    a.row_target = 1 << 30;
+    a.part = work;
+    a.bar = irls_batched_bar(work, d);
+    a.x_out = outv;
+    a.obj_out = outv + 64;
+  }
+  // signature of this batch: instances, parameters, arena
+  std::vector<char> sig;
+  auto put = [&sig](const void* p, size_t nb) {
+    const char* q = reinterpret_cast<const char*>(p);
+    sig.insert(sig.end(), q, q + nb);
+  };
+  put(&count, sizeof(count));
+  put(&dt, sizeof(dt));
+  put(&c->scratch, sizeof(c->scratch));
+  put(&c->scratch_bytes, sizeof(c->scratch_bytes));
+  put(&c->stream, sizeof(c->stream));
+  for (int i = 0; i < count; ++i) {
+    put(&inst[i], sizeof(fct_instance));
+    put(&items[i].prm, sizeof(fct_params));
+  }
+  const bool replay = c->bgraph && sig == c->bsig;
+  if (!replay) {
+    std::memcpy(c->bpinned, args.data(), (size_t)count * sizeof(IrlsArgs));
+    HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)count * sizeof(IrlsArgs),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->bgraph) {
+      (void)hipGraphExecDestroy(c->bgraph);
+      c->bgraph = nullptr;
+      c->bsig.clear();
+    }
+    // capture; if the runtime refuses, run the same sequence eagerly
+    bool captured = false;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+      const int est = batch_enqueue(c, inst, count, dt, items, args_dev, out_dev, out_bytes);
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+      if (est == FCT_OK && ee == hipSuccess && g) {
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+          c->bgraph = ex;
+          c->bsig = sig;
+          captured = true;
+        }
+      }
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+    }
+    if (captured) {
+      HIP_TRY(hipGraphLaunch(c->bgraph, c->stream));
+    } else {
+      if ((st = batch_enqueue(c, inst, count, dt, items, args_dev, out_dev, out_bytes))) return st;
+    }
+  } else {
+    HIP_TRY(hipGraphLaunch(c->bgraph, c->stream));
+  }
+  const int fl = read_flags(c);  // waits for the batch
+  const double* h = reinterpret_cast<const double*>(c->bpinned);
+  int first = FCT_OK;
+  int64_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    const int d = inst[i].d;
+    const double* row = h + (size_t)i * 72;
+    const int64_t Si = (int64_t)row[65];
+    int sti = (int)row[66];
+    if (Si > items[i].cap) sti = FCT_ERR_CAPACITY;
+    status[i] = sti;
+    for (int k = 0; k < d; ++k) x[off + k] = row[k];
+    off += d;
+    if (obj) obj[i] = row[64];
+    if (S) S[i] = Si;
+    if (s_used) s_used[i] = items[i].prm.s;
+    if (sti != FCT_OK && first == FCT_OK) first = sti;
+  }
+  if (fl) return fl;
+  return first;
 }
 
 int fct_rng_words(fct_ctx* c, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,

@@ -59,22 +59,6 @@ struct IrlsGeom {
   __host__ __device__ size_t lds_bytes() const { return fixed_bytes + (size_t)rmax * row_bytes; }
 };
 
-struct IrlsArgs {
-  const void* At;
-  const void* bt;
-  const double* w;
-  const int64_t* S_dev;
-  int64_t cap;
-  int64_t ldat;
-  int d;
-  int iters;
-  int row_target;  // coreset rows per active workgroup
-  double* part;   // 2 x gridDim.x x pstride
-  unsigned* bar;  // [0] arrival counter (zero at launch), [1] abort flag
-  double* x_out;
-  double* obj_out;
-  int* status;
-};
 
 size_t irls_work_doubles(int64_t S, int d) {
   (void)S;
@@ -294,8 +278,14 @@ __device__ __noinline__ bool gj_solve_wide(const double* G, const double* rhs, c
   return gj_solve<kGjMax>(er, ec, G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, z);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
+// BATCH: every workgroup solves its own instance, arr[blockIdx.x], alone (one
+// workgroup per instance, with its own barrier word, partials and status);
+// otherwise the grid cooperates on the instance a0.
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const IrlsArgs* __restrict__ arr) {
+  const IrlsArgs a = BATCH ? arr[blockIdx.x] : a0;
+  const int wg = BATCH ? 0 : (int)blockIdx.x;
+  const int gcount = BATCH ? 1 : (int)gridDim.x;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int flag_stop, flag_bad, flag_ok;
   const IrlsGeom g(a.d, sizeof(T));
@@ -321,12 +311,12 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
   int64_t pa = (S + a.row_target - 1) / a.row_target;
   const int64_t pmin = (S + g.rmax - 1) / g.rmax;
   if (pa < pmin) pa = pmin;
-  if (pa > (int64_t)gridDim.x) pa = gridDim.x;
+  if (pa > (int64_t)gcount) pa = gcount;
   if (pa < 1) pa = 1;
   const int P = (int)pa;
-  if ((int)blockIdx.x >= P) return;
+  if ((int)wg >= P) return;
   const int64_t per = (S + P - 1) / P;
-  const int64_t lo = min(S, (int64_t)blockIdx.x * per), hi = min(S, lo + per);
+  const int64_t lo = min(S, (int64_t)wg * per), hi = min(S, lo + per);
   const bool resident = hi - lo <= g.rmax;
 
   // sum of weights, in the same order in every workgroup
@@ -445,7 +435,7 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) G[(grp * nbp + pair) * 16 + e] = acc[e];
     __syncthreads();
-    double* mine = a.part + ((size_t)(it & 1) * P + blockIdx.x) * g.pstride;
+    double* mine = a.part + ((size_t)(it & 1) * P + wg) * g.pstride;
     for (int e = tid; e < nbp * 16; e += kIrlsThreads) {
       double s = 0.0;
       for (int gg = 0; gg < g.groups; ++gg) s += G[gg * nbp * 16 + e];
@@ -453,7 +443,7 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
     }
     if (tid == 0) mine[nbp * 16] = misc[8] + misc[9] + misc[10] + misc[11];
     if (!grid_barrier(a.bar, (unsigned)(it + 1) * (unsigned)P, &flag_ok)) {
-      if (blockIdx.x == 0 && tid == 0) *a.status = -5;
+      if (wg == 0 && tid == 0) *a.status = -5;
       break;
     }
     // all partials, fixed order, into the symmetric G and rhs; the loads of up
@@ -541,12 +531,12 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
     }
     __syncthreads();
     if (flag_bad) {
-      if (blockIdx.x == 0 && tid == 0) *a.status = -4;
+      if (wg == 0 && tid == 0) *a.status = -4;
       break;
     }
   }
   __syncthreads();
-  if (blockIdx.x == 0) {
+  if (wg == 0) {
     if (tid < d) a.x_out[tid] = xs[tid];
     if (tid == 0 && a.obj_out) *a.obj_out = misc[2];
   }
@@ -554,6 +544,39 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a) {
 
 __global__ void irls_reset_kernel(unsigned* bar) {
   if (threadIdx.x < 2) bar[threadIdx.x] = 0u;
+}
+
+__global__ void irls_reset_batched_kernel(const IrlsArgs* __restrict__ arr, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    arr[i].bar[0] = 0u;
+    arr[i].bar[1] = 0u;
+    *arr[i].status = 0;
+  }
+}
+
+size_t irls_batched_work_doubles(int d) {
+  const IrlsGeom g(d, sizeof(double));
+  return 2 * (size_t)g.pstride + 8;
+}
+
+unsigned* irls_batched_bar(double* work, int d) {
+  return reinterpret_cast<unsigned*>(work + irls_batched_work_doubles(d) - 8);
+}
+
+hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = kIrlsLdsBytes;
+  const void* fn = f64 ? (const void*)irls_kernel<double, true> : (const void*)irls_kernel<float, true>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  IrlsArgs none{};
+  hipLaunchKernelGGL(irls_reset_batched_kernel, dim3((count + 63) / 64), dim3(64), 0, st, arr, count);
+  if (f64)
+    hipLaunchKernelGGL((irls_kernel<double, true>), dim3(count), dim3(kIrlsThreads), lds, st, none, arr);
+  else
+    hipLaunchKernelGGL((irls_kernel<float, true>), dim3(count), dim3(kIrlsThreads), lds, st, none, arr);
+  return hipGetLastError();
 }
 
 static int irls_row_target() {
@@ -594,11 +617,12 @@ hipError_t launch_irls(const void* At, const void* bt, const double* w, const in
   a.obj_out = obj_out;
   a.status = status;
   const size_t lds = g.lds_bytes();
-  const void* fn = f64 ? (const void*)irls_kernel<double> : (const void*)irls_kernel<float>;
+  const void* fn = f64 ? (const void*)irls_kernel<double, false> : (const void*)irls_kernel<float, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(irls_reset_kernel, dim3(1), dim3(64), 0, st, a.bar);
-  void* args[] = {&a};
+  const IrlsArgs* none = nullptr;
+  void* args[] = {&a, &none};
   return hipLaunchCooperativeKernel(fn, dim3(P), dim3(kIrlsThreads), args, (unsigned)lds, st);
 }
 

@@ -35,6 +35,13 @@ class fct_params(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("irls_iters", ctypes.c_int32)]
 
 
+class fct_instance(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("A_lowp", ctypes.c_void_p),
+                ("b_lowp", ctypes.c_void_p), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("ld_lowp", ctypes.c_int64), ("d", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("prm", fct_params)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
@@ -65,6 +72,9 @@ def _load():
         "fct_l1_objective": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, PD, PD]),
         "l1_solve": (ctypes.c_int, [P, P, P, P, I64, I32, I64, ctypes.c_int, I32, PD, PD]),
         "l1_select": (ctypes.c_int, [P, P, P, I64, I64, U64, I64, P, P, PI64]),
+        "l1_regress_batched": (ctypes.c_int, [P, ctypes.POINTER(fct_instance), I32, ctypes.c_int, D,
+                                              PD, PD, PI64, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
         "fct_profile": (ctypes.c_int, [P, ctypes.c_int]),
         "fct_profile_read": (ctypes.c_int, [P, ctypes.c_int, PD, PI64]),
     }
@@ -80,7 +90,7 @@ EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream
             "fct_sketch_window",
             "l1_sample_probs", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
             "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
-            "fct_profile", "fct_profile_read")
+            "fct_profile", "fct_profile_read", "l1_regress_batched")
 
 
 def _check(st: int, where: str):
@@ -234,6 +244,43 @@ def l1_select(ctx, lam, sum_lambda, s_out, seed, cap):
     _check(_lib.l1_select(ctx.handle, _ptr(lam), _ptr(sum_lambda), n, int(s_out), seed, cap,
                           _ptr(idx), _ptr(w), ctypes.byref(S)), "l1_select")
     return idx[:S.value], w[:S.value], S.value
+
+
+def l1_regress_batched(ctx, items, eps=0.05):
+    """Solve many instances in one batch (one captured graph).
+
+    items: dicts with A ((d, n) tensor), b, prm (fct_params; s = 0 autotunes)
+    and optionally A_lowp, b_lowp (BF16 copies).  Returns (results, status):
+    results[i] = dict(x, obj, S, s, status)."""
+    count = len(items)
+    arr = (fct_instance * count)()
+    dt = None
+    for i, it in enumerate(items):
+        n, d, lda = _cm(it["A"])
+        lo = it.get("A_lowp")
+        ld_lo = _cm(lo)[2] if lo is not None else 0
+        arr[i] = fct_instance(A=_ptr(it["A"]), b=_ptr(it["b"]), A_lowp=_ptr(lo),
+                              b_lowp=_ptr(it.get("b_lowp")), n=n, lda=lda, ld_lowp=ld_lo, d=d,
+                              pad0=0, prm=it["prm"])
+        t = _dt(it["A"])
+        if dt is not None and t != dt:
+            raise ValueError("all instances of a batch share one element type")
+        dt = t
+    total_d = sum(int(it["A"].shape[0]) for it in items)
+    x = (ctypes.c_double * total_d)()
+    obj = (ctypes.c_double * count)()
+    S = (ctypes.c_int64 * count)()
+    s_used = (ctypes.c_int32 * count)()
+    status = (ctypes.c_int32 * count)()
+    st = _lib.l1_regress_batched(ctx.handle, arr, count, dt, eps, x, obj, S, s_used, status)
+    if st not in (0, -4, -6, -5) or (st != 0 and all(v == 0 for v in status)):
+        _check(st, "l1_regress_batched")
+    out, off = [], 0
+    for i, it in enumerate(items):
+        d = int(it["A"].shape[0])
+        out.append(dict(x=list(x[off:off + d]), obj=obj[i], S=S[i], s=s_used[i], status=status[i]))
+        off += d
+    return out, st
 
 
 def l1_solve(ctx, At, bt, w, iters=0):
