@@ -12,7 +12,8 @@ uses the pass-1 kernel's own device time, measured with HIP events around its
 launches on the stream it runs on; its HBM traffic comes from the committed
 counter summary when that summary was taken on the current kernel source.
 The CPU oracle runs the whole path (steps 1-8) once on the same workload on
-one host core.
+one host core.  The batching workload (256 instances of uneven n and d) is
+timed as one batch against the same instances solved one after another.
 """
 from __future__ import annotations
 
@@ -64,6 +65,85 @@ def committed_traffic(kernel_sources_sha: str, path: str):
         return None
 
 
+def bench_batched(F, ctx, count: int, steps: int, progress):
+    """The batching workload: `count` instances of uneven n and d solved in one
+    batch (captured graph, block size s autotuned per d), against the same
+    instances solved one after another by the single-instance path with the
+    block sizes the tuner chose."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import synth
+    ws = synth.batch_instances(count)
+    items = []
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        for k, (w, (A, b, _)) in enumerate(zip(ws, ex.map(lambda w: synth.generate(w, threads=1), ws))):
+            prm = F.params(s=0, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
+            items.append(dict(A=torch.from_numpy(A).cuda(), b=torch.from_numpy(b).cuda(),
+                              prm=prm, w=w))
+            if (k + 1) % 64 == 0:
+                progress(f"batch: generated and uploaded {k + 1} of {count} instances")
+    torch.cuda.synchronize()
+    rows = sum(w.n for w in ws)
+    nbytes = sum(2 * w.n * (w.d + 1) * 4 + w.n * 4 for w in ws)
+    t0 = time.perf_counter()
+    res, st = F.l1_regress_batched(ctx, items, eps=0.05)   # autotunes s and captures the graph
+    t_first = time.perf_counter() - t0
+    if st != 0:
+        bad = [(it["w"].seed, it["w"].n, it["w"].d, r["s"], r["status"])
+               for it, r in zip(items, res) if r["status"] != 0]
+        raise SystemExit(f"batched solve failed: status {st}; (seed, n, d, s, status): {bad}")
+    progress(f"batch: first call (autotune + capture + run) {t_first:.2f} s")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, st = F.l1_regress_batched(ctx, items, eps=0.05)
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / steps
+    progress(f"batch: {steps} timed replays, {dt_batch * 1e3:.2f} ms per batch")
+    seq_prm = [F.params(s=r["s"], r1=it["w"].r1, r2=it["w"].r2, s_out=it["w"].s_out,
+                        seed=it["w"].seed) for it, r in zip(items, res)]
+    for it, prm in zip(items, seq_prm):            # warm-up pass
+        F.l1_regress(ctx, it["A"], it["b"], prm, eps=0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seq = [F.l1_regress(ctx, it["A"], it["b"], prm, eps=0.05) for it, prm in zip(items, seq_prm)]
+    torch.cuda.synchronize()
+    dt_seq = (time.perf_counter() - t0) / steps
+    progress(f"batch: sequential single-instance path {dt_seq * 1e3:.2f} ms per batch")
+    same_S = all(r["S"] == S1 for r, (_, _, S1) in zip(res, seq))
+    dev = 0.0
+    for it, r, (x1, _, _) in zip(items, res, seq):
+        fb = F.fct_l1_objective(ctx, it["A"], it["b"], r["x"])
+        f1 = F.fct_l1_objective(ctx, it["A"], it["b"], x1)
+        dev = max(dev, abs(fb / f1 - 1))
+    ratios = []
+    for it, r in list(zip(items, res))[:: max(1, count // 16)]:
+        n = it["w"].n
+        x_ref, _ = F.l1_solve(ctx, it["A"], it["b"],
+                              torch.ones(n, dtype=torch.float64, device="cuda"), iters=120)
+        ratios.append(F.fct_l1_objective(ctx, it["A"], it["b"], r["x"]) /
+                      F.fct_l1_objective(ctx, it["A"], it["b"], x_ref))
+    tuned = {}
+    for it, r in zip(items, res):
+        tuned[str(it["w"].d)] = r["s"]
+    del items
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"batch-{count}: n ~ U[2^14, 2^20], d in {{8,16,32,64}}, f32, "
+                    "r1 = 8 d ceil(log2 d), r2 = 16, s_out = 250 (d+1), eps = 0.05",
+        "instances": count, "rows": rows, "algorithmic_bytes": nbytes,
+        "batched_ms": round(dt_batch * 1e3, 3), "sequential_ms": round(dt_seq * 1e3, 3),
+        "speedup": round(dt_seq / dt_batch, 3),
+        "batched_rows_per_s": round(rows / dt_batch), "sequential_rows_per_s": round(rows / dt_seq),
+        "batched_GBps": round(nbytes / dt_batch / 1e9, 1),
+        "batched_hbm_frac": round(nbytes / dt_batch / 1e9 / HBM_PEAK_GBS, 4),
+        "first_call_s": round(t_first, 3), "autotuned_s_by_d": tuned,
+        "same_coreset_sizes": same_S, "max_objective_deviation_batched_vs_single": dev,
+        "objective_ratio_vs_all_rows_solve_max": max(ratios),
+        "objective_ratio_sample": f"{len(ratios)} of {count} instances",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +154,8 @@ def main():
                     help="after timing, copy this many MiB device to device (counter scale)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solve")
+    ap.add_argument("--batch", type=int, default=256, help="instances of the batching workload (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -156,6 +238,10 @@ def main():
     traffic = committed_traffic(source_sha256(), os.path.join(
         ROOT, "profiles", "pmc_pass1_wave_kernel_tall-4194304x32-f32.txt"))
 
+    batched = None
+    if args.batch > 0:
+        batched = bench_batched(F, ctx, args.batch, args.batch_steps, progress)
+
     if not args.skip_cpu:
         progress("timing the CPU oracle")
     cpu = None if args.skip_cpu else cpu_oracle_run(A, b, w, args.cpu_rows)
@@ -189,6 +275,7 @@ def main():
             "pass2_bf16_GBps": round(pass2_bytes_bf16 / (p2b_ms * 1e-3) / 1e9, 1),
             "solve_ms": round(solve_ms, 4),
         },
+        "batched": batched,
         "end_to_end": {
             "plain_ms": round(dt_plain * 1e3, 4), "bf16_ms": round(dt_bf16 * 1e3, 4),
             "coreset_rows_plain": S_plain, "coreset_rows_bf16": S_bf16,

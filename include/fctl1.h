@@ -53,7 +53,8 @@ enum {
   FCT_ERR_OOM = -2,            /* device scratch could not be allocated        */
   FCT_ERR_NONFINITE = -3,      /* NaN or Inf met in an input                   */
   FCT_ERR_RANK_DEFICIENT = -4, /* |R_jj| <= tol ||R[:, j]||_2 (tol 1e-13 for FP64 input,
-                                  1e-5 for FP32), or a singular coreset system  */
+                                  1e-5 for FP32), or a singular coreset system
+                                  (the solver's first, unreweighted system)    */
   FCT_ERR_HIP = -5,            /* a HIP runtime call failed                    */
   FCT_ERR_CAPACITY = -6        /* realised coreset size exceeds the capacity   */
 };
@@ -160,7 +161,9 @@ int l1_coreset(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
 /*
  * l1_regress: the whole method.  eps documents the acceptance target; when
  * prm->s_out <= 0 the expected coreset size is ceil(20 q / eps).
- *   x: host double[d], the minimizer of the weighted coreset objective.
+ *   x: host double[d], the minimizer of the weighted coreset objective (the
+ *   iteratively reweighted solve stops at the current iterate when a later,
+ *   reweighted system loses a pivot; only a singular first system fails).
  *   obj: host double or NULL, the coreset objective sum_k w_k |A_k x - b_k|.
  *   S_out: host int64 or NULL, the realised coreset size.
  */

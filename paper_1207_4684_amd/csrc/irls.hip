@@ -5,15 +5,20 @@
 // sum_k w_k sqrt(r_k^2 + eta^2) (each step minimizes the quadratic majorant
 // sum_k w_k r_k^2 / sqrt(r_k^2 + eta^2), so the smoothed objective never
 // increases), with eta shrunk geometrically to a floor; the smoothed and the
-// exact objective differ by at most eta sum_k w_k.
+// exact objective differ by at most eta sum_k w_k.  The floor is 1e-6 of the
+// mean weighted residual, so the smoothing costs at most 1e-6 of the
+// objective: smaller floors give weights so uneven that FP64 rounding in the
+// Gram matrix makes the iterates wander.  The result is the iterate with the
+// lowest exact objective seen; at the floor the iteration stops once the
+// objective moves by at most 1e-9 relatively or has not improved three times.
 //
 // The whole iteration is one persistent cooperative kernel.  Each workgroup
 // owns a contiguous range of coreset rows and, per iteration, accumulates the
 // weighted Gram matrix of [A b] over its rows in 4x4 register blocks (FP64),
 // writes it as a partial, and meets the others at a grid barrier.  Every
 // workgroup then sums all partials in the same fixed order and runs the same
-// Cholesky solve, so all of them hold bit-identical x, objective and stopping
-// decision without a second barrier.  Partials are double-buffered by
+// Gauss-Jordan solve, so all of them hold bit-identical x, objective and
+// stopping decision without a second barrier.  Partials are double-buffered by
 // iteration parity: a workgroup can run at most one iteration ahead.
 #include "fct_device.h"
 #include "fct_kernels.h"
@@ -48,7 +53,7 @@ struct IrlsGeom {
     pstride = (E + 7) & ~7;
     const size_t g1 = (size_t)d * d, g2 = (size_t)groups * nbp * 16;
     gdoubles = ((g1 > g2 ? g1 : g2) + 1) & ~(size_t)1;  // keeps the vectors 16-byte aligned
-    fixed_bytes = (((gdoubles + 64 + 72 + 80 + 16 + 512 + 528 + 264 + 64 + 256) * sizeof(double)) + 15) &
+    fixed_bytes = (((gdoubles + 64 + 72 + 80 + 16 + 512 + 528 + 264 + 64 + 256 + 64) * sizeof(double)) + 15) &
                   ~(size_t)15;
     row_bytes = (size_t)W * elem + sizeof(double);
     rmax = (int)((kIrlsLdsBytes - fixed_bytes) / row_bytes);
@@ -287,7 +292,7 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
   const int wg = BATCH ? 0 : (int)blockIdx.x;
   const int gcount = BATCH ? 1 : (int)gridDim.x;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int flag_stop, flag_bad, flag_ok;
+  __shared__ int flag_stop, flag_bad, flag_ok, flag_best;
   const IrlsGeom g(a.d, sizeof(T));
   const int d = g.d, q = g.q, W = g.W, NB = g.NB, nbp = g.nbp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -295,12 +300,14 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
   double* rhs = G + g.gdoubles;
   double* xs = rhs + 64;    // 72: x, then -1 at d, zeros to the padded width
   double* sc = xs + 72;     // 80: d + 1 scales
-  double* misc = sc + 80;   // [0] sum w, [1] eta, [2] prev obj, [3] floor, [5] obj, [8..11] waves
+  double* misc = sc + 80;   // [0] sum w, [1] eta, [2] prev obj, [3] floor, [5] obj,
+                            // [6] best obj, [7] non-improving steps at the floor, [8..11] waves
   double* gjcol2 = misc + 16;    // 2 x 64 x 4: pivot columns of the Gauss-Jordan step
   double* gjrow2 = gjcol2 + 512; // 2 x 65 x 4: pivot rows, transposed
   double* gjt = gjrow2 + 528;    // 65 x 4: D^-1 times the pivot rows, transposed
   double* gjz = gjt + 264;       // 64: solution
   double* gjd = gjz + 64;        // 256: per-thread dummy slots
+  double* bx = gjd + 256;        // 64: the best iterate
   double* om = reinterpret_cast<double*>(smem + g.fixed_bytes);
   T* zr = reinterpret_cast<T*>(om + g.rmax);
   const T* At = (const T*)a.At;
@@ -333,6 +340,8 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
     misc[1] = 0.0;
     misc[2] = 0.0;
     misc[3] = 0.0;
+    misc[6] = HUGE_VAL;
+    misc[7] = 0.0;
   }
 
   // entries of the augmented n4 x (n4 + 1) system owned by this thread in the
@@ -490,12 +499,20 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
     if (tid == 0) {
       const double obj = misc[5];
       double e_c = misc[1];
-      const double floor_now = 1e-9 * obj / misc[0];
+      const double floor_now = 1e-6 * obj / misc[0];
+      const bool at_floor = e_c > 0.0 && e_c <= misc[3] * 1.0000001;
       int stop = 0;
+      const int best = obj < misc[6];  // false for a non-finite objective
+      if (best) {
+        misc[6] = obj;
+        misc[7] = 0.0;
+      } else if (at_floor) {
+        misc[7] += 1.0;
+      }
       if (e_c <= 0.0) {
         e_c = obj / misc[0];  // first smoothing level: mean weighted residual
       } else {
-        if (e_c <= misc[3] * 1.0000001 && fabs(misc[2] - obj) <= 1e-9 * obj) stop = 1;
+        if (at_floor && (fabs(misc[2] - obj) <= 1e-9 * obj || misc[7] >= 3.0)) stop = 1;
         e_c = fmax(floor_now, 0.3 * e_c);
       }
       if (!(obj > 0.0) || it >= a.iters) stop = 1;  // exact fit, non-finite, or budget spent
@@ -503,9 +520,11 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
       misc[2] = obj;
       misc[1] = e_c;
       flag_stop = stop;
+      flag_best = best;
       flag_bad = 0;
     }
     __syncthreads();
+    if (flag_best && tid < d) bx[tid] = xs[tid];
     if (flag_stop) break;
     // Jacobi equilibration S = diag(G)^-1/2, then block Gauss-Jordan on the
     // augmented n4 x (n4 + 1) system [S G S | S rhs] (identity rows and
@@ -531,14 +550,22 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
     }
     __syncthreads();
     if (flag_bad) {
-      if (wg == 0 && tid == 0) *a.status = -4;
+      // The first system carries only the coreset weights: a failed pivot
+      // there means the coreset is singular.  Later systems are reweighted
+      // by 1/sqrt(r^2 + eta^2), whose spread near the optimum can push a
+      // Schur pivot of a full-rank coreset below the threshold; the best
+      // iterate so far is then the result.
+      if (it == 0 && wg == 0 && tid == 0) *a.status = -4;
       break;
     }
   }
   __syncthreads();
   if (wg == 0) {
-    if (tid < d) a.x_out[tid] = xs[tid];
-    if (tid == 0 && a.obj_out) *a.obj_out = misc[2];
+    // the best iterate; before any objective was formed (a failed barrier on
+    // the first step) that is the starting point x = 0
+    const bool any = misc[6] < HUGE_VAL;
+    if (tid < d) a.x_out[tid] = any ? bx[tid] : 0.0;
+    if (tid == 0 && a.obj_out) *a.obj_out = any ? misc[6] : misc[2];
   }
 }
 

@@ -3,6 +3,7 @@
     python -m paper_1207_4684_amd.profile_summary stats DB [--match SUBSTR]
     python -m paper_1207_4684_amd.profile_summary traffic FETCH_DB WRITE_DB \
         --kernel SUBSTR --copy-bytes N --algorithmic-bytes B
+    python -m paper_1207_4684_amd.profile_summary pmc FETCH_DB WRITE_DB
 
 ``stats`` prints calls, total, average, minimum and maximum device time per
 kernel from the kernel trace.  ``traffic`` reads one database collected with
@@ -113,6 +114,20 @@ def cmd_traffic(args):
     print(f"source_sha256: {source_sha256()}")
 
 
+def cmd_pmc(args):
+    fetch = counter_per_dispatch(args.fetch_db, "FETCH_SIZE")
+    write = counter_per_dispatch(args.write_db, "WRITE_SIZE")
+    print(f"{'kernel':80s} {'dispatches':>10s} {'fetch_KiB':>12s} {'write_KiB':>12s} {'hbm_MB':>10s}")
+    rows = []
+    for k in set(fetch) | set(write):
+        f, fn, _ = fetch.get(k, (0.0, 0, 0.0))
+        w, wn, _ = write.get(k, (0.0, 0, 0.0))
+        rows.append((k, max(fn, wn), f, w, (2.0 * f + w) * 1024.0 / 1e6))
+    rows.sort(key=lambda r: -r[4])
+    for k, n, f, w, mb in rows:
+        print(f"{_short(k, 80):80s} {n:10d} {f:12.1f} {w:12.1f} {mb:10.2f}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -127,8 +142,11 @@ def main(argv=None):
     t.add_argument("--algorithmic-bytes", type=int, default=0)
     t.add_argument("--copy-kernel", default="copy",
                    help="substring naming the copy kernel of known size")
+    m = sub.add_parser("pmc")
+    m.add_argument("fetch_db")
+    m.add_argument("write_db")
     args = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[args.cmd](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "pmc": cmd_pmc}[args.cmd](args)
 
 
 if __name__ == "__main__":

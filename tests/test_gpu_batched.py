@@ -4,7 +4,11 @@ Each instance of a batch drawn like the batching workload (n in [2^14, 2^20],
 d in {8, 16, 32, 64}, r1 = 8 d ceil(log2 d), s_out = 250 q) must give what
 the single-instance path gives with the same parameters: the same coreset
 size and an objective equal to solver precision (the batched solve runs on
-one workgroup per instance, the single path on several).  A replay of the
+one workgroup per instance, the single path on several, so their sums are
+rounded in different orders).  Solver precision: the smoothed objective
+with eta at its floor, 1e-6 of the mean weighted residual, exceeds the exact
+one by at most 1e-6 of the objective, so each solve ends within that of the
+coreset optimum.  A replay of the
 captured graph must reproduce the first call, autotuned block sizes must be
 among the candidates, and a small instance must meet the (1 + eps) bound
 against the exact LP optimum.
@@ -65,7 +69,7 @@ def test_batched_matches_single_instances_and_replays(F, ctx):
         fb2 = F.fct_l1_objective(ctx, it["A"], it["b"], r2["x"])
         print(f"n={w.n} d={w.d} s={r['s']} S={r['S']} batched/single {fb / f1 - 1:.2e}")
         assert r["S"] == S1 and r2["S"] == S1
-        assert abs(fb / f1 - 1) <= 1e-8 and abs(fb2 / fb - 1) <= 1e-8
+        assert abs(fb / f1 - 1) <= 1e-6 and abs(fb2 / fb - 1) <= 1e-6
 
 
 def test_batched_one_plus_eps_small_instance(F, ctx):
@@ -79,3 +83,28 @@ def test_batched_one_plus_eps_small_instance(F, ctx):
     _, fopt = l1.lp(At, b64)
     for r in res:
         assert l1.objective(At, b64, np.array(r["x"])) <= (1 + 0.05) * fopt
+
+
+def test_solver_shapes_agree_on_ill_conditioned_coreset(F, ctx, monkeypatch):
+    """Instance 206 of the batching workload (n = 25110, d = 32): its coreset
+    makes the reweighted systems badly conditioned near the optimum.  One
+    workgroup streaming every row (the batched shape) and the cooperative grid
+    must both end within the smoothing bound of the exact LP optimum."""
+    import math
+    w = synth.batch_instances(207)[206]
+    A, b, _ = synth.generate(w)
+    prm = F.params(s=256, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
+    cap = min(w.n, 2 * w.s_out + 8 * int(math.sqrt(w.s_out)) + 1024)
+    At, bt, wt, idx, S = F.l1_coreset(ctx, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(),
+                                      prm, cap)
+    Ah = At.double().cpu().numpy()
+    bh = bt.double().cpu().numpy()
+    wh = wt.cpu().numpy()
+    _, fopt = l1.lp(Ah, bh, wh)
+    x_many, o_many = F.l1_solve(ctx, At.t(), bt, wt)
+    monkeypatch.setenv("FCTL1_IRLS_WGS", "1")
+    x_one, o_one = F.l1_solve(ctx, At.t(), bt, wt)
+    for x in (x_many, x_one):
+        f = l1.objective(Ah, bh, x, wh)
+        print(f"S={S} f/fopt - 1 = {f / fopt - 1:.3e}")
+        assert f <= fopt * (1 + 1e-6)
