@@ -129,6 +129,9 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int r1, int* er
   }
   int cmax = (int)((budget - fixed) / per_col);
   if (cmax > q) cmax = q;
+  // widest slices: every slice re-reads the random table and re-runs the
+  // per-tile set-up, which costs more than the lanes a width that is not a
+  // multiple of 4 leaves idle (their adds are masked off)
   p.nslices = (q + cmax - 1) / cmax;
   p.c = (q + p.nslices - 1) / p.nslices;
   p.nslices = (q + p.c - 1) / p.c;
@@ -220,9 +223,14 @@ struct SketchBufs {
 };
 
 template <typename C>
-void carve_sketch(C& cv, const Pass1Plan& p, int q, int r1, size_t es, bool want_r) {
+void carve_sketch(C& cv, const Pass1Plan& p, int64_t n_pad, int q, int r1, size_t es, bool want_r) {
   cv.template take<char>((size_t)p.nranges * q * r1 * es);
   cv.template take<double>((size_t)r1 * q);
+  if (p.kind == 1) {
+    const int64_t rows = pi1_table_rows(n_pad);
+    cv.template take<uint4>((size_t)rows / 4);
+    cv.template take<float4>((size_t)rows / 2);
+  }
   if (want_r) cv.template take<double>(qr_work_doubles(r1, q));
 }
 
@@ -234,6 +242,13 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   const size_t es = esize(dt);
   void* partials = cv.take<char>((size_t)p.nranges * q * r1 * es);
   double* Yd = cv.take<double>((size_t)r1 * q);
+  uint4* tab_keys = nullptr;
+  float4* tab_c = nullptr;
+  if (p.kind == 1) {
+    const int64_t rows = pi1_table_rows(n_pad);
+    tab_keys = cv.take<uint4>((size_t)rows / 4);
+    tab_c = cv.take<float4>((size_t)rows / 2);
+  }
   Pass1Args a{};
   a.A = A;
   a.b = b;
@@ -252,8 +267,12 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.sign_flip = (flags & FCT_FLAG_NO_SIGN_FLIP) ? 0 : 1;
   a.row0g = row0g;
   a.partials = partials;
+  a.tab_keys = tab_keys;
+  a.tab_c = tab_c;
   prof_begin(c, 0);
   if (p.kind == 1) {
+    HIP_TRY(launch_pi1_table(seed, 0, row0g, pi1_table_rows(n_pad), s, r1, tab_keys, tab_c,
+                             c->stream));
     const bool vec_ok = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0) &&
                         (!b || (((uintptr_t)b & 15) == 0));
     HIP_TRY(launch_pass1_wave(a, p, vec_ok, c->stream));
@@ -497,7 +516,7 @@ int fct_sketch(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fct
   const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   Measure m;
-  carve_sketch(m, p, q, r1, esize(dt), R != nullptr);
+  carve_sketch(m, p, n_pad, q, r1, esize(dt), R != nullptr);
   if ((st = ensure_scratch(c, m.off))) return st;
   Carve cv(c->scratch);
   return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, R, nullptr, p);
@@ -515,7 +534,7 @@ int fct_sketch_window(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t l
   const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   Measure m;
-  carve_sketch(m, p, q, r1, esize(dt), false);
+  carve_sketch(m, p, n_pad, q, r1, esize(dt), false);
   if ((st = ensure_scratch(c, m.off))) return st;
   Carve cv(c->scratch);
   return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, nullptr, nullptr, p, row0);
@@ -601,7 +620,7 @@ static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype 
   m.take<double>(1);
   const size_t base = m.off;
   Measure a, bb, cc;
-  carve_sketch(a, p, q, prm->r1, esize(dt), true);
+  carve_sketch(a, p, n_pad, q, prm->r1, esize(dt), true);
   carve_probs(bb, q, prm->r2, n, lowp ? kPass2BF16 : (dt == FCT_F64 ? kPass2F64 : kPass2F32));
   carve_select(cc, n);
   size_t mx = a.off;
@@ -812,7 +831,7 @@ int time_sketch(fct_ctx* c, const fct_instance& in, fct_dtype dt, int s, float* 
   const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, in.prm.r1, esize(dt), &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   Measure m;
-  carve_sketch(m, p, q, in.prm.r1, esize(dt), false);
+  carve_sketch(m, p, n_pad, q, in.prm.r1, esize(dt), false);
   int st;
   if ((st = ensure_scratch(c, m.off))) return st;
   hipEvent_t e0, e1;

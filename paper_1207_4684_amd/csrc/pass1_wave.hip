@@ -2,15 +2,20 @@
 // Pi1 = 4 B C H~ (section "FCT1 Construction"; n/s Hadamard transforms of
 // size s, a diagonal Cauchy scaling and a hash scatter with 2n non-zeros).
 //
+// The random part of Pi1 (bucket and Cauchy of both stacked copies of every
+// row) does not depend on X.  pi1_table_kernel draws it once per sketch into
+// a table of 12 bytes per row (one Philox call per pair of stacked
+// positions), so the column slices below read it instead of drawing it again.
+//
 // A workgroup of 8 waves owns a range of rows and a slice of c columns of
 // X = [A, -b], with a private r1 x c FP64 accumulator in LDS (FP64 LDS atomic
 // adds: on gfx950 they sustain ~9x the rate of FP32 LDS atomic adds, and the
 // sums are FP64).  Each wave takes a
 // contiguous run of 256-row tiles and works on them alone (no workgroup
 // barrier inside the run):
-//   1. one Philox call per pair of stacked positions gives, for the tile's
-//      256 rows, the (bucket, Cauchy) of both copies of every row; 4 rows per
-//      lane, stored to the wave's table in LDS and shared by every column;
+//   1. the tile's table entries, 4 rows per lane (loaded one tile ahead), go
+//      to the wave's table in LDS as (bucket * c, Cauchy), shared by every
+//      column;
 //   2. the slice's columns are processed 4 at a time, 16 lanes per column; a
 //      lane holds 16 rows {4L + i + 64k} of its column (float4 loads, the
 //      next group's loads issued before the current group is processed);
@@ -100,6 +105,31 @@ __device__ __forceinline__ void load_group(const Pass1Args& a, int c0, int cs, i
 
 __device__ __forceinline__ void acc_add(double* p, float v) { atomicAdd(p, (double)v); }
 
+// Rows [4 i, 4 i + 4) of the table, local row 0 at global row row0g.  Rows 2m
+// and 2m + 1 of one block hold stacked positions 2c and 2c + 1 of both
+// halves, so one Philox call per half serves two rows.
+__global__ void pi1_table_kernel(uint64_t seed, uint32_t instance, int64_t row0g, int64_t groups,
+                                 int log2s, uint32_t r1, float scale_h, uint4* __restrict__ keys,
+                                 float4* __restrict__ cc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= groups) return;
+  const uint64_t s = 1ull << log2s;
+  const uint64_t j0 = (uint64_t)row0g + 4 * (uint64_t)i;
+  const uint64_t kA = h_position(j0, log2s), kB = h_position(j0 + 2, log2s);
+  const uint4 wa = stream_words(seed, kStreamPi1, kA >> 1, instance);
+  const uint4 wb = stream_words(seed, kStreamPi1, kB >> 1, instance);
+  const uint4 xa = stream_words(seed, kStreamPi1, (kA + s) >> 1, instance);
+  const uint4 xb = stream_words(seed, kStreamPi1, (kB + s) >> 1, instance);
+  keys[i] = make_uint4(bucket_from_word(wa.x, r1) | (bucket_from_word(xa.x, r1) << 16),
+                       bucket_from_word(wa.z, r1) | (bucket_from_word(xa.z, r1) << 16),
+                       bucket_from_word(wb.x, r1) | (bucket_from_word(xb.x, r1) << 16),
+                       bucket_from_word(wb.z, r1) | (bucket_from_word(xb.z, r1) << 16));
+  cc[2 * i] = make_float4(cauchy_from_word(wa.y) * scale_h, cauchy_from_word(xa.y) * 4.0f,
+                          cauchy_from_word(wa.w) * scale_h, cauchy_from_word(xa.w) * 4.0f);
+  cc[2 * i + 1] = make_float4(cauchy_from_word(wb.y) * scale_h, cauchy_from_word(xb.y) * 4.0f,
+                              cauchy_from_word(wb.w) * scale_h, cauchy_from_word(xb.w) * 4.0f);
+}
+
 __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, int vec_ok) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int c0 = blockIdx.y * a.c;
@@ -118,12 +148,18 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
   const int64_t w1 = min(row1, w0 + sub);
   const int g = lane >> 4, L = lane & 15;
   const int ngroups = (cs + 3) >> 2;
-  const float scale_h = 4.0f / sqrtf((float)a.s);
-  const uint64_t s = (uint64_t)a.s;
   const bool vok = vec_ok != 0;
 
   float v[16], vn[16];
-  if (w0 < w1) load_group(a, c0, cs, w0, 0, g, L, vok, v);
+  uint4 tk = make_uint4(0, 0, 0, 0);
+  float4 tc0 = make_float4(0.f, 0.f, 0.f, 0.f), tc1 = tc0;
+  if (w0 < w1) {
+    load_group(a, c0, cs, w0, 0, g, L, vok, v);
+    const int64_t t4 = (w0 >> 2) + lane;
+    tk = a.tab_keys[t4];
+    tc0 = a.tab_c[2 * t4];
+    tc1 = a.tab_c[2 * t4 + 1];
+  }
   int64_t sign_base = w0;
 
   for (int64_t tile = w0; tile < w1; tile += kTile) {
@@ -136,30 +172,24 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
       }
     }
     {
-      // RNG table for rows tile + 4 lane + {0,1,2,3}: positions come in pairs
-      const uint64_t j0 = (uint64_t)(a.row0g + tile) + 4 * lane;
-      const uint64_t kA = h_position(j0, a.log2s), kB = h_position(j0 + 2, a.log2s);
-      const uint4 wa = stream_words(a.seed, kStreamPi1, kA >> 1, a.instance);
-      const uint4 wb = stream_words(a.seed, kStreamPi1, kB >> 1, a.instance);
-      const uint4 xa = stream_words(a.seed, kStreamPi1, (kA + s) >> 1, a.instance);
-      const uint4 xb = stream_words(a.seed, kStreamPi1, (kB + s) >> 1, a.instance);
-      const uint32_t r1 = (uint32_t)a.r1;
-      const uint32_t ucs = (uint32_t)cs;  // table holds bucket * cs, the cell row offset
-      uint4 h0, h1, i0, i1;
-      h0.x = __umul24(bucket_from_word(wa.x, r1), ucs); h0.y = __float_as_uint(cauchy_from_word(wa.y) * scale_h);
-      h0.z = __umul24(bucket_from_word(wa.z, r1), ucs); h0.w = __float_as_uint(cauchy_from_word(wa.w) * scale_h);
-      h1.x = __umul24(bucket_from_word(wb.x, r1), ucs); h1.y = __float_as_uint(cauchy_from_word(wb.y) * scale_h);
-      h1.z = __umul24(bucket_from_word(wb.z, r1), ucs); h1.w = __float_as_uint(cauchy_from_word(wb.w) * scale_h);
-      i0.x = __umul24(bucket_from_word(xa.x, r1), ucs); i0.y = __float_as_uint(cauchy_from_word(xa.y) * 4.0f);
-      i0.z = __umul24(bucket_from_word(xa.z, r1), ucs); i0.w = __float_as_uint(cauchy_from_word(xa.w) * 4.0f);
-      i1.x = __umul24(bucket_from_word(xb.x, r1), ucs); i1.y = __float_as_uint(cauchy_from_word(xb.y) * 4.0f);
-      i1.z = __umul24(bucket_from_word(xb.z, r1), ucs); i1.w = __float_as_uint(cauchy_from_word(xb.w) * 4.0f);
+      // table entries of rows tile + 4 lane + {0, 1, 2, 3}; then the next tile's
+      const uint32_t ucs = (uint32_t)cs;  // the LDS table holds bucket * cs, the cell row offset
       uint4* eh = reinterpret_cast<uint4*>(&W.entH[4 * lane]);
       uint4* ei = reinterpret_cast<uint4*>(&W.entI[4 * lane]);
-      eh[0] = h0;
-      eh[1] = h1;
-      ei[0] = i0;
-      ei[1] = i1;
+      eh[0] = make_uint4(__umul24(tk.x & 0xFFFFu, ucs), __float_as_uint(tc0.x),
+                         __umul24(tk.y & 0xFFFFu, ucs), __float_as_uint(tc0.z));
+      eh[1] = make_uint4(__umul24(tk.z & 0xFFFFu, ucs), __float_as_uint(tc1.x),
+                         __umul24(tk.w & 0xFFFFu, ucs), __float_as_uint(tc1.z));
+      ei[0] = make_uint4(__umul24(tk.x >> 16, ucs), __float_as_uint(tc0.y),
+                         __umul24(tk.y >> 16, ucs), __float_as_uint(tc0.w));
+      ei[1] = make_uint4(__umul24(tk.z >> 16, ucs), __float_as_uint(tc1.y),
+                         __umul24(tk.w >> 16, ucs), __float_as_uint(tc1.w));
+      if (tile + kTile < w1) {
+        const int64_t t4 = ((tile + kTile) >> 2) + lane;
+        tk = a.tab_keys[t4];
+        tc0 = a.tab_c[2 * t4];
+        tc1 = a.tab_c[2 * t4 + 1];
+      }
     }
     wave_sync();
     const int soff = (int)((tile - sign_base) >> 5);
@@ -169,7 +199,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
       else if (tile + kTile < w1) load_group(a, c0, cs, tile + kTile, 0, g, L, vok, vn);
       const int colr = grp * 4 + g;
       const bool cact = colr < cs;
-      const int col = cact ? colr : cs - 1;  // idle lanes add zeros to a valid cell
+      const int col = cact ? colr : cs - 1;  // idle lanes (masked off at the adds) stay in bounds
       // sign D(j) (and the minus of the b column) as a sign-bit xor
       const uint32_t negb = (cact && c0 + col == a.d) ? 0x80000000u : 0u;
 #pragma unroll
@@ -188,10 +218,12 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
         const int t0 = 4 * L + 64 * k;
         const uint4 e01 = *reinterpret_cast<const uint4*>(&W.entI[t0]);
         const uint4 e23 = *reinterpret_cast<const uint4*>(&W.entI[t0 + 2]);
-        acc_add(&acc[e01.x + col], __uint_as_float(e01.y) * v[4 * k + 0]);
-        acc_add(&acc[e01.z + col], __uint_as_float(e01.w) * v[4 * k + 1]);
-        acc_add(&acc[e23.x + col], __uint_as_float(e23.y) * v[4 * k + 2]);
-        acc_add(&acc[e23.z + col], __uint_as_float(e23.w) * v[4 * k + 3]);
+        if (cact) {
+          acc_add(&acc[e01.x + col], __uint_as_float(e01.y) * v[4 * k + 0]);
+          acc_add(&acc[e01.z + col], __uint_as_float(e01.w) * v[4 * k + 1]);
+          acc_add(&acc[e23.x + col], __uint_as_float(e23.y) * v[4 * k + 2]);
+          acc_add(&acc[e23.z + col], __uint_as_float(e23.w) * v[4 * k + 3]);
+        }
       }
       // butterflies over row bits 0, 1 (register bits 0, 1) and 6, 7 (register bits 2, 3)
       if (a.log2s > 0) reg_stage(v, 0);
@@ -218,7 +250,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const uint2 e = W.entH[4 * r + base];
-          acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[r]);
+          if (cact) acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[r]);
         }
       } else {
         // s <= 4: rows stay at t = 4 L + i + 64 k
@@ -227,7 +259,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const uint2 e = W.entH[4 * L + i + 64 * k];
-            acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[4 * k + i]);
+            if (cact) acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[4 * k + i]);
           }
         }
       }
@@ -249,6 +281,19 @@ size_t pass1_wave_lds(int r1, int c) {
 }
 
 int pass1_wave_rows_quantum() { return kWaves * kTile; }
+
+int64_t pi1_table_rows(int64_t n_pad) { return (n_pad + kTile - 1) / kTile * kTile; }
+
+hipError_t launch_pi1_table(uint64_t seed, uint32_t instance, int64_t row0g, int64_t rows, int s,
+                            int r1, uint4* keys, float4* cc, hipStream_t st) {
+  const int64_t groups = rows / 4;
+  const unsigned blocks = (unsigned)((groups + 255) / 256);
+  int log2s = 0;
+  while ((1 << log2s) < s) ++log2s;
+  hipLaunchKernelGGL(pi1_table_kernel, dim3(blocks), dim3(256), 0, st, seed, instance, row0g,
+                     groups, log2s, (uint32_t)r1, 4.0f / sqrtf((float)s), keys, cc);
+  return hipGetLastError();
+}
 
 hipError_t launch_pass1_wave(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)pass1_wave_kernel,

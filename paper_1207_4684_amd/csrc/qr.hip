@@ -122,6 +122,18 @@ __global__ void qr_finish_kernel(const double* __restrict__ Rin, int64_t ldin, i
   }
 }
 
+static hipError_t launch_qr_panel(const double* in, int64_t m, int q, int64_t ldin, int P,
+                                  double* out, int64_t np, hipStream_t st) {
+  const int prow = (int)(m < P ? m : P);
+  const size_t lds = (size_t)prow * q * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)qr_panel_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)np), dim3(kQrThreads), lds, st, in, m, q,
+                     ldin, P, out, np * q);
+  return hipGetLastError();
+}
+
 size_t qr_work_doubles(int r1, int q) {
   const int P = qr_panel_rows(q);
   size_t tot = 0;
@@ -144,14 +156,7 @@ hipError_t launch_qr(const double* Y, int r1, int q, double* work, double* R, do
   hipError_t e;
   while (true) {
     const int64_t np = (m + P - 1) / P;
-    const int prow = (int)(m < P ? m : P);
-    const size_t lds = (size_t)prow * q * sizeof(double);
-    e = hipFuncSetAttribute((const void*)qr_panel_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)np), dim3(kQrThreads), lds, st, in, m, q,
-                       ldin, P, out, np * q);
-    e = hipGetLastError();
+    e = launch_qr_panel(in, m, q, ldin, P, out, np, st);
     if (e != hipSuccess) return e;
     if (np == 1) break;
     in = out;
