@@ -12,6 +12,8 @@
 #include "fct_device.h"
 #include "fct_kernels.h"
 
+#include <cstdlib>
+
 namespace fctl1 {
 
 static constexpr int kP2Threads = 256;
@@ -112,33 +114,49 @@ __global__ void __launch_bounds__(kP2Threads) pass2_valu_kernel(Pass2Args a) {
 
 // MFMA form for FP32 and BF16 data.  Lambda^T = M^T X^T is formed on the
 // matrix cores: A = M^T (16 r2-columns x K) is constant and held in registers,
-// B = X^T (K x 16 rows) is loaded straight from the column-major X (16
-// consecutive rows of one column per 16 lanes), and D holds, in lane l,
-// register i, the value (row l % 16, r2-column 4 (l / 16) + i).  FP32 uses
+// B = X^T (K x 16 rows) comes straight from the column-major X.  Each wave
+// takes 64-row tiles; lane l loads rows 4 (l % 16) .. 4 (l % 16) + 3 of its
+// columns in one vector load per column (all of a tile's loads are issued
+// before the first product, so a wave keeps a whole tile in flight), and
+// MFMA tile i of the four takes rows 4 n + i.  D holds, in lane l, register
+// i, the value (tile row l % 16, r2-column 4 (l / 16) + i).  FP32 uses
 // v_mfma_f32_16x16x4f32 (K = 4 per instruction), BF16 uses
 // v_mfma_f32_16x16x16bf16_1k (K = 16, products exact, FP32 accumulation).
-// Each wave takes 64-row tiles; D goes through LDS so that lane l then owns
-// row l, takes |.|, sorts its r2 values and stores the median.
+// D goes through LDS so that lane l then owns row l of the tile, takes |.|,
+// sorts its r2 values and stores the median.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
-template <int MT>
+__device__ __forceinline__ float f4_comp(const float4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// LDS rows of one wave: MFMA tile i (rows 4 n + i of the 64-row tile) is
+// stored in its own block of 16 rows; blocks are 4 floats apart beyond a
+// multiple of 64 banks so the lane-per-row reads do not collide.
+template <int LS>
+__device__ __forceinline__ float* p2_tile_rows(float* L, int i) { return L + i * (16 * LS + 4); }
+
+// KS: K-steps of 4 columns compiled in (the smallest of 3, 5, 9, 17 that
+// covers q; columns past q read as zero).
+template <int MT, int KS>
 __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a) {
   constexpr int R2P = 16 * MT, LS = R2P + 4;
-  __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS];
+  __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS + 12];
   __shared__ double red[kP2Threads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r2p = r2_padded(a.r2);
   const float* __restrict__ Mf = reinterpret_cast<const float*>(a.M);
   const float* __restrict__ A = reinterpret_cast<const float*>(a.A);
   const float* __restrict__ bv = reinterpret_cast<const float*>(a.b);
-  const int ks_n = (a.q + 3) >> 2;
+  const bool vec = (a.lda & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(bv) & 15) == 0;
   // A operand: M[k][m], k = 4 ks + lane / 16, m = lane % 16 + 16 mt
-  float am[MT][17];
+  float am[MT][KS];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int ks = 0; ks < 17; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + (lane >> 4), m = (lane & 15) + 16 * mt;
       am[mt][ks] = (k < a.q && m < r2p) ? Mf[k * r2p + m] : 0.0f;
     }
@@ -148,34 +166,50 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
   for (int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave; t < ntiles;
        t += (int64_t)gridDim.x * (kP2Threads / 64)) {
     const int64_t r0 = t << 6;
+    const int n4 = lane & 15, g = lane >> 4;
+    const int64_t rb = r0 + 4 * n4;
+    // rows rb .. rb + 3 of column 4 ks + g, one float4 per column, all issued
+    // before the first product; MFMA tile i takes row rb + i
+    float4 xv[KS];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int64_t row = r0 + 16 * nt + (lane & 15);
-      const bool rin = row < a.n;
-      float xb[17];
-#pragma unroll
-      for (int ks = 0; ks < 17; ++ks) {
-        const int c = 4 * ks + (lane >> 4);
-        float v = 0.0f;
-        if (ks < ks_n && rin && c < a.q) v = c < a.d ? A[row + (int64_t)c * a.lda] : -bv[row];
-        xb[ks] = v;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + g;
+      float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (c < a.q) {
+        const float* col = c < a.d ? A + (int64_t)c * a.lda : bv;
+        if (vec && rb + 3 < a.n) {
+          x4 = *reinterpret_cast<const float4*>(col + rb);
+        } else {
+          if (rb < a.n) x4.x = col[rb];
+          if (rb + 1 < a.n) x4.y = col[rb + 1];
+          if (rb + 2 < a.n) x4.z = col[rb + 2];
+          if (rb + 3 < a.n) x4.w = col[rb + 3];
+        }
+        if (c == a.d) x4 = make_float4(-x4.x, -x4.y, -x4.z, -x4.w);
       }
+      xv[ks] = x4;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float* Li = p2_tile_rows<LS>(L, i);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ks = 0; ks < 17; ++ks)
-          if (ks < ks_n) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[mt][ks], xb[ks], acc, 0, 0, 0);
-        *reinterpret_cast<f32x4*>(L + (16 * nt + (lane & 15)) * LS + 16 * mt + 4 * (lane >> 4)) = acc;
+        for (int ks = 0; ks < KS; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(am[mt][ks], f4_comp(xv[ks], i), acc, 0, 0, 0);
+        *reinterpret_cast<f32x4*>(Li + n4 * LS + 16 * mt + 4 * g) = acc;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane = 4 n + i holds row r0 + lane
+    const float* Lr = p2_tile_rows<LS>(L, lane & 3) + (lane >> 2) * LS;
     float v[R2P];
 #pragma unroll
     for (int j = 0; j < R2P; j += 4) {
-      const f32x4 q4 = *reinterpret_cast<const f32x4*>(L + lane * LS + j);
+      const f32x4 q4 = *reinterpret_cast<const f32x4*>(Lr + j);
       v[j] = q4[0];
       v[j + 1] = q4[1];
       v[j + 2] = q4[2];
@@ -205,22 +239,24 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
   if (threadIdx.x == 0) a.wg_sums[blockIdx.x] = s;
 }
 
-template <int MT>
+// KS: K-steps of 16 columns compiled in (ceil(q / 16), at most 5).
+template <int MT, int KS>
 __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a) {
   constexpr int R2P = 16 * MT, LS = R2P + 4;
-  __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS];
+  __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS + 12];
   __shared__ double red[kP2Threads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r2p = r2_padded(a.r2);
   const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(a.A);
   const uint16_t* __restrict__ bv = reinterpret_cast<const uint16_t*>(a.b);
-  const int ks_n = (a.q + 15) >> 4;
+  const bool vec = (a.lda & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 7) == 0 &&
+                   (reinterpret_cast<uintptr_t>(bv) & 7) == 0;
   // A operand: M[k][m] as BF16, k = 16 ks + 4 (lane / 16) + j, m = lane % 16 + 16 mt
-  s16x4 am[MT][5];
+  s16x4 am[MT][KS];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int ks = 0; ks < 5; ++ks)
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = 16 * ks + 4 * (lane >> 4) + j, m = (lane & 15) + 16 * mt;
@@ -232,37 +268,58 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
   for (int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave; t < ntiles;
        t += (int64_t)gridDim.x * (kP2Threads / 64)) {
     const int64_t r0 = t << 6;
+    const int n4 = lane & 15, g = lane >> 4;
+    const int64_t rb = r0 + 4 * n4;
+    // rows rb .. rb + 3 of columns 16 ks + 4 g + j: one 8-byte load per
+    // column; MFMA tile i takes row rb + i
+    uint2 xv[KS][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int64_t row = r0 + 16 * nt + (lane & 15);
-      const bool rin = row < a.n;
-      s16x4 xb[5];
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-      for (int ks = 0; ks < 5; ++ks)
+      for (int j = 0; j < 4; ++j) {
+        const int c = 16 * ks + 4 * g + j;
+        uint2 x4 = make_uint2(0u, 0u);
+        if (c < a.q) {
+          const uint16_t* col = c < a.d ? A + (int64_t)c * a.lda : bv;
+          if (vec && rb + 3 < a.n) {
+            x4 = *reinterpret_cast<const uint2*>(col + rb);
+          } else {
+            const uint32_t e0 = rb < a.n ? col[rb] : 0u, e1 = rb + 1 < a.n ? col[rb + 1] : 0u;
+            const uint32_t e2 = rb + 2 < a.n ? col[rb + 2] : 0u, e3 = rb + 3 < a.n ? col[rb + 3] : 0u;
+            x4 = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+          }
+          if (c == a.d) x4 = make_uint2(x4.x ^ 0x80008000u, x4.y ^ 0x80008000u);
+        }
+        xv[ks][j] = x4;
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float* Li = p2_tile_rows<LS>(L, i);
+      s16x4 xb[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int c = 16 * ks + 4 * (lane >> 4) + j;
-          uint16_t v = 0;
-          if (ks < ks_n && rin && c < a.q)
-            v = c < a.d ? A[row + (int64_t)c * a.lda] : (uint16_t)(bv[row] ^ 0x8000u);
-          xb[ks][j] = (short)v;
+          const uint32_t w = (i < 2) ? xv[ks][j].x : xv[ks][j].y;
+          xb[ks][j] = (short)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
         }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ks = 0; ks < 5; ++ks)
-          if (ks < ks_n) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[mt][ks], xb[ks], acc, 0, 0, 0);
-        *reinterpret_cast<f32x4*>(L + (16 * nt + (lane & 15)) * LS + 16 * mt + 4 * (lane >> 4)) = acc;
+        for (int ks = 0; ks < KS; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[mt][ks], xb[ks], acc, 0, 0, 0);
+        *reinterpret_cast<f32x4*>(Li + n4 * LS + 16 * mt + 4 * g) = acc;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float* Lr = p2_tile_rows<LS>(L, lane & 3) + (lane >> 2) * LS;
     float v[R2P];
 #pragma unroll
     for (int j = 0; j < R2P; j += 4) {
-      const f32x4 q4 = *reinterpret_cast<const f32x4*>(L + lane * LS + j);
+      const f32x4 q4 = *reinterpret_cast<const f32x4*>(Lr + j);
       v[j] = q4[0];
       v[j + 1] = q4[1];
       v[j + 2] = q4[2];
@@ -294,9 +351,12 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
 
 int pass2_grid(int64_t n, int kind) {
   if (kind != kPass2F64) {
-    // MFMA forms: 64-row tiles per wave, about four workgroups per CU
+    // MFMA forms: 64-row tiles per wave, grid-stride over the tiles
+    int64_t cap = 1024;
+    if (const char* e = std::getenv("FCTL1_P2_WGS")) cap = std::atoll(e);
+    if (cap < 1) cap = 1;
     int64_t want = (n + 255) / 256;
-    if (want > 1024) want = 1024;
+    if (want > cap) want = cap;
     return (int)(want < 1 ? 1 : want);
   }
   int64_t want = (n + kP2Threads - 1) / kP2Threads;
@@ -324,11 +384,41 @@ hipError_t launch_pass2(const Pass2Args& a, int kind, hipStream_t st) {
   if (a.q > 65 || a.r2 > 32) return hipErrorInvalidValue;
   const int grid = pass2_grid(a.n, kind);
   if (kind == kPass2BF16) {
-    if (r2p <= 16) hipLaunchKernelGGL((pass2_mfma_bf16_kernel<1>), dim3(grid), dim3(kP2Threads), 0, st, a);
-    else hipLaunchKernelGGL((pass2_mfma_bf16_kernel<2>), dim3(grid), dim3(kP2Threads), 0, st, a);
+    const int ks = (a.q + 15) >> 4;
+#define P2_BF16(MT, KS) hipLaunchKernelGGL((pass2_mfma_bf16_kernel<MT, KS>), dim3(grid), dim3(kP2Threads), 0, st, a)
+    if (r2p <= 16) {
+      switch (ks) {
+        case 1: P2_BF16(1, 1); break;
+        case 2: P2_BF16(1, 2); break;
+        case 3: P2_BF16(1, 3); break;
+        case 4: P2_BF16(1, 4); break;
+        default: P2_BF16(1, 5); break;
+      }
+    } else {
+      switch (ks) {
+        case 1: P2_BF16(2, 1); break;
+        case 2: P2_BF16(2, 2); break;
+        case 3: P2_BF16(2, 3); break;
+        case 4: P2_BF16(2, 4); break;
+        default: P2_BF16(2, 5); break;
+      }
+    }
+#undef P2_BF16
   } else {
-    if (r2p <= 16) hipLaunchKernelGGL((pass2_mfma_f32_kernel<1>), dim3(grid), dim3(kP2Threads), 0, st, a);
-    else hipLaunchKernelGGL((pass2_mfma_f32_kernel<2>), dim3(grid), dim3(kP2Threads), 0, st, a);
+    const int ks = (a.q + 3) >> 2;
+#define P2_F32(MT, KS) hipLaunchKernelGGL((pass2_mfma_f32_kernel<MT, KS>), dim3(grid), dim3(kP2Threads), 0, st, a)
+    if (r2p <= 16) {
+      if (ks <= 3) P2_F32(1, 3);
+      else if (ks <= 5) P2_F32(1, 5);
+      else if (ks <= 9) P2_F32(1, 9);
+      else P2_F32(1, 17);
+    } else {
+      if (ks <= 3) P2_F32(2, 3);
+      else if (ks <= 5) P2_F32(2, 5);
+      else if (ks <= 9) P2_F32(2, 9);
+      else P2_F32(2, 17);
+    }
+#undef P2_F32
   }
   return hipGetLastError();
 }
