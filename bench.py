@@ -12,7 +12,8 @@ uses the pass-1 kernel's own device time, measured with HIP events around its
 launches on the stream it runs on; its HBM traffic comes from the committed
 counter summary when that summary was taken on the current kernel source.
 The CPU oracle runs the whole path (steps 1-8) once on the same workload on
-one host core.  The batching workload (256 instances of uneven n and d) is
+one host core.  --workload precision|large times the same steps on the
+33,554,432 x 64 or 268,435,456 x 16 workloads.  The batching workload (256 instances of uneven n and d) is
 timed as one batch against the same instances solved one after another.
 """
 from __future__ import annotations
@@ -156,6 +157,8 @@ def main():
     ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solve")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batching workload (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--workload", default="tall", choices=("tall", "precision", "large"),
+                    help="workload of the timed steps (the bench line is quoted on tall)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -170,7 +173,7 @@ def main():
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    w = synth.TALL
+    w = {"tall": synth.TALL, "precision": synth.PRECISION, "large": synth.LARGE}[args.workload]
     q = w.d + 1
     A, b, _ = synth.generate(w)
     progress(f"generated {w.name}")
@@ -235,8 +238,13 @@ def main():
         del src, dst
 
     from paper_1207_4684_amd.profile_summary import source_sha256
-    traffic = committed_traffic(source_sha256(), os.path.join(
-        ROOT, "profiles", "pmc_pass1_wave_kernel_tall-4194304x32-f32.txt"))
+    wave_form = w.s <= 2048  # FP32 data: the wave-level sketch kernel, else the workgroup tile
+    p1_kernel = ("pass1_wave_kernel" if w.s <= 256 else "pass1_block_kernel") if wave_form \
+        else "pass1_kernel"
+    traffic = None
+    if wave_form:
+        traffic = committed_traffic(source_sha256(), os.path.join(
+            ROOT, "profiles", f"pmc_pass1_wave_kernel_{w.name}.txt"))
 
     batched = None
     if args.batch > 0:
@@ -264,7 +272,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(p1_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(p1_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": "pass1_wave_kernel (FCT1 sketch)", "kernel_ms": round(p1_ms, 5),
+                     "kernel": f"{p1_kernel} (FCT1 sketch, with its random-table kernel)"
+                     if wave_form else f"{p1_kernel} (FCT1 sketch)", "kernel_ms": round(p1_ms, 5),
                      "algorithmic_bytes": pass1_bytes},
         "cpu_baseline": cpu,
         "passes": {

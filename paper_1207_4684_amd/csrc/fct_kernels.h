@@ -23,12 +23,12 @@ struct Pass1Args {
   int32_t sign_flip;
   int64_t row0g;       // global index of local row 0 (random streams are indexed globally)
   void* partials;      // [nranges][q][r1] of the input type
-  const uint4* tab_keys;  // wave kernel: per row, bucket of the H copy | bucket of the I copy << 16
+  const uint4* tab_keys;  // wave kernel: per row, H bucket | sign of D(j) << 15 | I bucket << 16
   const float4* tab_c;    // wave kernel: per row, (4 C_H / sqrt(s), 4 C_I), two rows per float4
 };
 
 struct Pass1Plan {
-  int kind;            // 0: workgroup-tile kernel, 1: wave-level kernel (FP32, s <= 256)
+  int kind;            // 0: workgroup-tile kernel, 1: wave-level kernel (FP32, s <= 2048)
   bool vec_ok;         // 16-byte aligned columns (wave kernel float4 loads)
   int threads;
   int rpt;             // rows per thread per chunk
@@ -42,11 +42,14 @@ struct Pass1Plan {
 hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStream_t st);
 size_t pass1_wave_lds(int r1, int c);
 int pass1_wave_rows_quantum();
+// whether the wave form for block size s reads the signs of D from the table
+// (s > 256) or draws them itself
+bool pass1_wave_signs_in_table(int s);
 // rows of the wave kernel's random table for n_pad padded rows (whole tiles)
 int64_t pi1_table_rows(int64_t n_pad);
 // the table: keys[rows / 4] (uint4), cc[rows / 2] (float4); rows a multiple of 4
 hipError_t launch_pi1_table(uint64_t seed, uint32_t instance, int64_t row0g, int64_t rows, int s,
-                            int r1, uint4* keys, float4* cc, hipStream_t st);
+                            int r1, int sign_flip, uint4* keys, float4* cc, hipStream_t st);
 hipError_t launch_pass1_wave(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st);
 hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
                                   double* Yd, int* flag, bool f64, hipStream_t st);

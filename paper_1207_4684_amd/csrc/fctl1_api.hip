@@ -153,7 +153,7 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int r1, int* er
 
 Pass1Plan make_pass1_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, size_t es,
                           int* err) {
-  if (es == sizeof(float) && s <= 256 && !c->p1_force_tile) {
+  if (es == sizeof(float) && s <= 2048 && r1 <= 32768 && !c->p1_force_tile) {
     Pass1Plan w = make_wave_plan(c, n_pad, q, r1, err);
     if (!*err) return w;
   }
@@ -271,7 +271,8 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.tab_c = tab_c;
   prof_begin(c, 0);
   if (p.kind == 1) {
-    HIP_TRY(launch_pi1_table(seed, 0, row0g, pi1_table_rows(n_pad), s, r1, tab_keys, tab_c,
+    HIP_TRY(launch_pi1_table(seed, 0, row0g, pi1_table_rows(n_pad), s, r1,
+                             pass1_wave_signs_in_table(s) ? a.sign_flip : 0, tab_keys, tab_c,
                              c->stream));
     const bool vec_ok = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0) &&
                         (!b || (((uintptr_t)b & 15) == 0));

@@ -110,6 +110,8 @@ SKETCH_CASES = [
     (40000, 7, 1024, 256, np.float32, True, True),
     (20000, 3, 4096, 64, np.float32, True, False),
     (30000, 64, 512, 4096, np.float32, True, True),
+    (24000, 5, 2048, 128, np.float32, True, True),
+    (10000, 9, 512, 1024, np.float32, True, False),
 ]
 
 
