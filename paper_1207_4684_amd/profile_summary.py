@@ -10,8 +10,8 @@ kernel from the kernel trace.  ``traffic`` reads one database collected with
 ``--pmc FETCH_SIZE`` and one with ``--pmc WRITE_SIZE`` (KiB per dispatch),
 scales each by what the same counter reads for the largest dispatch of the
 copy kernel (``--copy-kernel``, a copy of ``--copy-bytes`` bytes reads and
-writes that many bytes) in the same run, and prints the HBM bytes per launch of the kernel
-whose name contains ``--kernel``, with the SHA-256 of the sources that build
+writes that many bytes) in the same run, and prints the HBM bytes per launch of the kernels
+whose names contain the ``--kernel`` substrings (summed), with the SHA-256 of the sources that build
 it so a reader can tell whether the figures still describe the current code.
 """
 from __future__ import annotations
@@ -85,22 +85,25 @@ def _copy_value(table, pattern):
 def cmd_traffic(args):
     fetch = counter_per_dispatch(args.fetch_db, "FETCH_SIZE")
     write = counter_per_dispatch(args.write_db, "WRITE_SIZE")
-    fk = [k for k in fetch if args.kernel in k]
-    wk = [k for k in write if args.kernel in k]
-    if not fk or not wk:
-        raise SystemExit(f"kernel {args.kernel!r} not found in the counter databases")
-    f_val, f_n, _ = fetch[fk[0]]
-    w_val, w_n, _ = write[wk[0]]
     cf, cf_name = _copy_value(fetch, args.copy_kernel.lower())
     cw, cw_name = _copy_value(write, args.copy_kernel.lower())
     f_scale = args.copy_bytes / (cf * 1024.0)
     w_scale = args.copy_bytes / (cw * 1024.0)
-    hbm = f_val * 1024.0 * f_scale + w_val * 1024.0 * w_scale
-    print(f"kernel: {fk[0]}")
-    print(f"dispatches_fetch: {f_n}")
-    print(f"dispatches_write: {w_n}")
-    print(f"fetch_kib_per_dispatch: {f_val:.1f}")
-    print(f"write_kib_per_dispatch: {w_val:.1f}")
+    # one launch of the measured unit is one dispatch of each named kernel
+    hbm = 0.0
+    for sub in args.kernel:
+        fk = [k for k in fetch if sub in k]
+        wk = [k for k in write if sub in k]
+        if not fk or not wk:
+            raise SystemExit(f"kernel {sub!r} not found in the counter databases")
+        f_val, f_n, _ = fetch[fk[0]]
+        w_val, w_n, _ = write[wk[0]]
+        hbm += f_val * 1024.0 * f_scale + w_val * 1024.0 * w_scale
+        print(f"kernel: {fk[0]}")
+        print(f"dispatches_fetch: {f_n}")
+        print(f"dispatches_write: {w_n}")
+        print(f"fetch_kib_per_dispatch: {f_val:.1f}")
+        print(f"write_kib_per_dispatch: {w_val:.1f}")
     print(f"copy_kernel: {cf_name}")
     print(f"copy_bytes: {args.copy_bytes}")
     print(f"copy_fetch_kib: {cf:.1f}")
@@ -137,7 +140,8 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("fetch_db")
     t.add_argument("write_db")
-    t.add_argument("--kernel", required=True)
+    t.add_argument("--kernel", required=True, action="append",
+                   help="substring of a kernel name; repeat to sum kernels launched together")
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--algorithmic-bytes", type=int, default=0)
     t.add_argument("--copy-kernel", default="copy",
