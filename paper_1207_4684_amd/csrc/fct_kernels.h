@@ -40,7 +40,7 @@ struct Pass1Plan {
 };
 
 hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStream_t st);
-size_t pass1_wave_lds(int r1, int c);
+size_t pass1_wave_lds(int r1, int c, int s);
 int pass1_wave_rows_quantum();
 // whether the wave form for block size s reads the signs of D from the table
 // (s > 256) or draws them itself

@@ -114,14 +114,14 @@ int ensure_scratch(fct_ctx* c, size_t bytes) {
   return FCT_OK;
 }
 
-Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int r1, int* err) {
+Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, int* err) {
   Pass1Plan p{};
   p.kind = 1;
   p.threads = 512;
   p.rpt = 1;
   *err = 0;
   const size_t budget = c->p1_lds_budget ? c->p1_lds_budget : c->lds_optin;
-  const size_t fixed = pass1_wave_lds(r1, 0) + 16;
+  const size_t fixed = pass1_wave_lds(r1, 0, s) + 16;
   const size_t per_col = (size_t)r1 * sizeof(double);
   if (budget <= fixed + per_col) {
     *err = 1;
@@ -135,7 +135,7 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int r1, int* er
   p.nslices = (q + cmax - 1) / cmax;
   p.c = (q + p.nslices - 1) / p.nslices;
   p.nslices = (q + p.c - 1) / p.c;
-  p.lds = pass1_wave_lds(r1, p.c);
+  p.lds = pass1_wave_lds(r1, p.c, s);
   int per_cu = (int)((size_t)(160 * 1024) / p.lds);
   if (per_cu < 1) per_cu = 1;
   const int64_t target = (int64_t)c->cus * per_cu * c->p1_waves_of_wgs;
@@ -154,7 +154,7 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int r1, int* er
 Pass1Plan make_pass1_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, size_t es,
                           int* err) {
   if (es == sizeof(float) && s <= 2048 && r1 <= 32768 && !c->p1_force_tile) {
-    Pass1Plan w = make_wave_plan(c, n_pad, q, r1, err);
+    Pass1Plan w = make_wave_plan(c, n_pad, q, s, r1, err);
     if (!*err) return w;
   }
   Pass1Plan p{};

@@ -19,16 +19,18 @@
 //      next group's loads issued before the current group is processed);
 //   3. the sign D(j) is applied, the I-half copies are added into their
 //      buckets (LDS atomics), the Walsh-Hadamard butterflies over the row
-//      bits held in registers (0, 1, 6, 7) are done in place, one transpose
-//      through LDS brings row bits 2-5 into registers for the remaining
-//      butterflies, and the H-half copies are added into their buckets.
+//      bits held in registers (0, 1, 6, 7) are done in place, those over row
+//      bits 2-5 (the lane index within 16) pair lanes through DPP moves, and
+//      the H-half copies are added into their buckets.  No LDS beyond the
+//      accumulator and the per-wave tables is touched, which leaves room
+//      for wider column slices.
 // pass1_wave_kernel (s <= 256): a 256-row tile holds whole blocks, each wave
 // streams its own contiguous eighth of the range and never waits for the
 // others, and it draws the signs of D itself (a Philox call per 128 rows).
 // pass1_block_kernel (256 < s <= 2048): the workgroup walks its range in
 // steps of 8 tiles, wave w taking tile w, so a block spans s / 256
 // neighbouring waves; row bits 8-10 are the wave index and their butterflies
-// pair the waves through LDS at workgroup barriers.  Its signs come with the
+// pair the waves through an LDS exchange buffer at workgroup barriers.  Its signs come with the
 // table (bit 15 of a row's key).  Either way the accumulator is written once
 // per workgroup and the partials are summed in a fixed order by the
 // reduction kernel.
@@ -41,17 +43,41 @@ namespace {
 
 constexpr int kTile = 256;
 constexpr int kWaves = 8;
-constexpr int kTrStride = 272;          // per column group; 16 banks apart
+constexpr int kXch = 16 * 64;           // floats per wave in the cross-wave exchange (s > 256)
 constexpr int kSignRows = 4096;         // rows covered by one refresh of sign words (s <= 256)
 
 struct WaveLds {
   uint2 entH[kTile];                    // {bucket * c, bits of 4 C / sqrt(s)} of the H-half copy
   uint2 entI[kTile];                    // {bucket * c, bits of 4 C} of the I-half copy
   uint32_t sgn[kSignRows / 32];         // sign words (s <= 256 form)
-  float tr[4 * kTrStride];
 };
 
-__device__ __forceinline__ int trpad(int t) { return t + ((t >> 6) << 2); }
+// v of the lane whose L differs in bit B (L = lane % 16: DPP within a row of
+// 16 lanes).  Bit 0: quad_perm [1,0,3,2]; bit 1: quad_perm [2,3,0,1]; bit 2:
+// row_half_mirror (L ^ 7) then quad_perm [3,2,1,0] (^ 3); bit 3: row_ror:8.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int B>
+__device__ __forceinline__ float lane_xor(float v) {
+  if constexpr (B == 0) return dpp_f<0xB1>(v);
+  else if constexpr (B == 1) return dpp_f<0x4E>(v);
+  else if constexpr (B == 2) return dpp_f<0x1B>(dpp_f<0x141>(v));
+  else return dpp_f<0x128>(v);
+}
+
+// butterflies along bit B of L (row bit 2 + B): the lower lane keeps x + y,
+// the upper one x - y, as p + (+-1) v with one rounding, like x + y and x - y
+template <int B>
+__device__ __forceinline__ void lane_stage(float (&v)[16], int L) {
+  const float sg = ((L >> B) & 1) ? -1.0f : 1.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float p = lane_xor<B>(v[r]);
+    v[r] = fmaf(sg, v[r], p);
+  }
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -245,37 +271,22 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
       if (a.log2s > 1) reg_stage(v, 1);
       if (a.log2s > 6) reg_stage(v, 2);
       if (a.log2s > 7) reg_stage(v, 3);
-      // transpose: lane bits (row bits 2-5) <-> register bits
-      if (a.log2s > 2) {
-        float* tr = W.tr + g * kTrStride;
+      // butterflies over row bits 2-5, held in the lane index, across lanes
+      if (a.log2s > 2) lane_stage<0>(v, L);
+      if (a.log2s > 3) lane_stage<1>(v, L);
+      if (a.log2s > 4) lane_stage<2>(v, L);
+      if (a.log2s > 5) lane_stage<3>(v, L);
+      // H-half copies: rows t = 4 L + i + 64 k, as for the I half
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          *reinterpret_cast<float4*>(&tr[trpad(4 * L + 64 * k)]) =
-              make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-        wave_sync();
-        const int base = (L & 3) + 64 * (L >> 2);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = tr[trpad(4 * r + base)];
-        wave_sync();
-        if (a.log2s > 2) reg_stage(v, 0);
-        if (a.log2s > 3) reg_stage(v, 1);
-        if (a.log2s > 4) reg_stage(v, 2);
-        if (a.log2s > 5) reg_stage(v, 3);
-        // H-half copies: rows t = 4 r + (L & 3) + 64 (L >> 2)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const uint2 e = W.entH[4 * r + base];
-          if (cact) acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[r]);
-        }
-      } else {
-        // s <= 4: rows stay at t = 4 L + i + 64 k
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint2 e = W.entH[4 * L + i + 64 * k];
-            if (cact) acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[4 * k + i]);
-          }
+      for (int k = 0; k < 4; ++k) {
+        const int t0 = 4 * L + 64 * k;
+        const uint4 e01 = *reinterpret_cast<const uint4*>(&W.entH[t0]);
+        const uint4 e23 = *reinterpret_cast<const uint4*>(&W.entH[t0 + 2]);
+        if (cact) {
+          acc_add(&acc[e01.x + col], __uint_as_float(e01.y) * v[4 * k + 0]);
+          acc_add(&acc[e01.z + col], __uint_as_float(e01.w) * v[4 * k + 1]);
+          acc_add(&acc[e23.x + col], __uint_as_float(e23.y) * v[4 * k + 2]);
+          acc_add(&acc[e23.z + col], __uint_as_float(e23.w) * v[4 * k + 3]);
         }
       }
 #pragma unroll
@@ -299,6 +310,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
   const size_t acc_bytes = (((size_t)a.r1 * a.c * sizeof(double)) + 15) & ~size_t(15);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveLds& W = reinterpret_cast<WaveLds*>(smem_raw + acc_bytes)[wave];
+  float* xch = reinterpret_cast<float*>(smem_raw + acc_bytes + kWaves * sizeof(WaveLds));
   for (int i = threadIdx.x; i < a.r1 * cs; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
 
@@ -392,55 +404,40 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
       if (a.log2s > 1) reg_stage(v, 1);
       if (a.log2s > 6) reg_stage(v, 2);
       if (a.log2s > 7) reg_stage(v, 3);
-      // transpose: lane bits (row bits 2-5) <-> register bits
-      if (a.log2s > 2) {
-        float* tr = W.tr + g * kTrStride;
+      // butterflies over row bits 2-5, held in the lane index, across lanes
+      if (a.log2s > 2) lane_stage<0>(v, L);
+      if (a.log2s > 3) lane_stage<1>(v, L);
+      if (a.log2s > 4) lane_stage<2>(v, L);
+      if (a.log2s > 5) lane_stage<3>(v, L);
+      // row bits >= 8 live in the wave index: each stage pairs wave w with
+      // w ^ (1 << (bit - 8)) through the exchange buffers (the lower-row wave
+      // keeps a + b, the upper one b - a)
+      for (int bit = 8; bit < a.log2s; ++bit) {
+        const int pw = wave ^ (1 << (bit - 8));
+        const bool upper = (wave >> (bit - 8)) & 1;
+        float* mine = xch + wave * kXch;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          *reinterpret_cast<float4*>(&tr[trpad(4 * L + 64 * k)]) =
-              make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-        wave_sync();
-        const int base = (L & 3) + 64 * (L >> 2);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = tr[trpad(4 * r + base)];
-        wave_sync();
-        if (a.log2s > 2) reg_stage(v, 0);
-        if (a.log2s > 3) reg_stage(v, 1);
-        if (a.log2s > 4) reg_stage(v, 2);
-        if (a.log2s > 5) reg_stage(v, 3);
-        // row bits >= 8 live in the wave index: each stage pairs wave w with
-        // w ^ (1 << (bit - 8)) through the waves' transpose buffers (the
-        // lower-row wave keeps a + b, the upper one b - a)
-        for (int bit = 8; bit < a.log2s; ++bit) {
-          float* mine = W.tr;
-          const int pw = wave ^ (1 << (bit - 8));
-          const bool upper = (wave >> (bit - 8)) & 1;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) mine[r * 64 + lane] = v[r];
-          __syncthreads();
-          const float* theirs = reinterpret_cast<WaveLds*>(smem_raw + acc_bytes)[pw].tr;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const float o = theirs[r * 64 + lane];
-            v[r] = upper ? o - v[r] : v[r] + o;
-          }
-          __syncthreads();
-        }
-        // H-half copies: rows t = 4 r + (L & 3) + 64 (L >> 2)
+        for (int r = 0; r < 16; ++r) mine[r * 64 + lane] = v[r];
+        __syncthreads();
+        const float* theirs = xch + pw * kXch;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const uint2 e = W.entH[4 * r + base];
-          if (cact) acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[r]);
+          const float o = theirs[r * 64 + lane];
+          v[r] = upper ? o - v[r] : v[r] + o;
         }
-      } else {
-        // s <= 4: rows stay at t = 4 L + i + 64 k
+        __syncthreads();
+      }
+      // H-half copies: rows t = 4 L + i + 64 k, as for the I half
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint2 e = W.entH[4 * L + i + 64 * k];
-            if (cact) acc_add(&acc[e.x + col], __uint_as_float(e.y) * v[4 * k + i]);
-          }
+      for (int k = 0; k < 4; ++k) {
+        const int t0 = 4 * L + 64 * k;
+        const uint4 e01 = *reinterpret_cast<const uint4*>(&W.entH[t0]);
+        const uint4 e23 = *reinterpret_cast<const uint4*>(&W.entH[t0 + 2]);
+        if (cact) {
+          acc_add(&acc[e01.x + col], __uint_as_float(e01.y) * v[4 * k + 0]);
+          acc_add(&acc[e01.z + col], __uint_as_float(e01.w) * v[4 * k + 1]);
+          acc_add(&acc[e23.x + col], __uint_as_float(e23.y) * v[4 * k + 2]);
+          acc_add(&acc[e23.z + col], __uint_as_float(e23.w) * v[4 * k + 3]);
         }
       }
       const bool have_next = grp + 1 < ngroups ? act : more;
@@ -457,8 +454,9 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
   }
 }
 
-size_t pass1_wave_lds(int r1, int c) {
-  return ((((size_t)r1 * c * sizeof(double)) + 15) & ~size_t(15)) + kWaves * sizeof(WaveLds);
+size_t pass1_wave_lds(int r1, int c, int s) {
+  return ((((size_t)r1 * c * sizeof(double)) + 15) & ~size_t(15)) + kWaves * sizeof(WaveLds) +
+         (s > kTile ? (size_t)kWaves * kXch * sizeof(float) : 0);
 }
 
 int pass1_wave_rows_quantum() { return kWaves * kTile; }
