@@ -112,6 +112,33 @@ __device__ __forceinline__ float sign_from_words(uint4 wv, uint64_t j) {
   return ((word >> (j & 31u)) & 1u) ? -1.0f : 1.0f;
 }
 
+// Sum over the 64 lanes of a wave, the same value in every lane; every lane
+// must be active.  Within each row of 16 lanes: DPP xor 1 and xor 2
+// (quad_perm [1,0,3,2], [2,3,0,1]), then the half-row mirror (lane i with
+// 7 - i: the other quad) and the row mirror (i with 15 - i: the other half);
+// the four row sums are read as scalars and added in a fixed order.  About a
+// tenth of the latency of six cross-lane shuffles through the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
 template <typename T> struct FmaT;
 template <> struct FmaT<float> {
   static __device__ __forceinline__ float fma(float a, float b, float c) { return fmaf(a, b, c); }

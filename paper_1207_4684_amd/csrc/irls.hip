@@ -437,8 +437,7 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
       if (!resident) __syncthreads();
     }
     // workgroup partial: sum the row groups in order, then publish
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) objp += __shfl_xor(objp, o, 64);
+    objp = wave_sum_dpp(objp);
     if (lane == 0) misc[8 + wave] = objp;
     if (gram_thread)
 #pragma unroll

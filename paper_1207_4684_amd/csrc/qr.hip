@@ -19,11 +19,7 @@ static constexpr int kQrLdsDoubles = 16000;  // 125 KB panel budget
 
 static int qr_panel_rows(int q) { return kQrLdsDoubles / q; }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 // Householder QR of rows [p P, p P + m) of In (m_total x q, ld = ldin);
 // writes the q x q upper R into rows [p q, p q + q) of Out (ld = ldout).
