@@ -4,8 +4,8 @@
 // iteratively reweighted least squares on the smoothed objective
 // sum_k w_k sqrt(r_k^2 + eta^2) (each step minimizes the quadratic majorant
 // sum_k w_k r_k^2 / sqrt(r_k^2 + eta^2), so the smoothed objective never
-// increases), with eta shrunk geometrically to a floor; the smoothed and the
-// exact objective differ by at most eta sum_k w_k.  The floor is 1e-6 of the
+// increases), with eta shrunk by 5x per step to a floor; the smoothed and
+// the exact objective differ by at most eta sum_k w_k.  The floor is 1e-6 of the
 // mean weighted residual, so the smoothing costs at most 1e-6 of the
 // objective: smaller floors give weights so uneven that FP64 rounding in the
 // Gram matrix makes the iterates wander.  The result is the iterate with the
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const I
         e_c = obj / misc[0];  // first smoothing level: mean weighted residual
       } else {
         if (at_floor && (fabs(misc[2] - obj) <= 1e-9 * obj || misc[7] >= 3.0)) stop = 1;
-        e_c = fmax(floor_now, 0.3 * e_c);
+        e_c = fmax(floor_now, 0.2 * e_c);
       }
       if (!(obj > 0.0) || it >= a.iters) stop = 1;  // exact fit, non-finite, or budget spent
       misc[3] = floor_now;
