@@ -66,6 +66,28 @@ def committed_traffic(kernel_sources_sha: str, path: str):
         return None
 
 
+def measured_copy_gbps(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Read + write bandwidth of a device-to-device copy of `mib` MiB (torch's
+    copy on its current stream, timed with events on that stream): the
+    streaming bandwidth this machine reaches, beside the nominal HBM peak."""
+    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def bench_batched(F, ctx, count: int, steps: int, progress):
     """The batching workload: `count` instances of uneven n and d solved in one
     batch (captured graph, block size s autotuned per d), against the same
@@ -246,6 +268,9 @@ def main():
         traffic = committed_traffic(source_sha256(), os.path.join(
             ROOT, "profiles", f"pmc_pass1_wave_kernel_{w.name}.txt"))
 
+    copy_gbps = measured_copy_gbps(torch)
+    progress(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
+
     batched = None
     if args.batch > 0:
         batched = bench_batched(F, ctx, args.batch, args.batch_steps, progress)
@@ -274,7 +299,9 @@ def main():
                      "traffic": None if traffic is None else round(traffic),
                      "kernel": f"{p1_kernel} (FCT1 sketch, with its random-table kernel)"
                      if wave_form else f"{p1_kernel} (FCT1 sketch)", "kernel_ms": round(p1_ms, 5),
-                     "algorithmic_bytes": pass1_bytes},
+                     "algorithmic_bytes": pass1_bytes,
+                     "measured_copy_GBps": round(copy_gbps, 1),
+                     "frac_of_measured_copy": round(p1_gbs / copy_gbps, 4)},
         "cpu_baseline": cpu,
         "passes": {
             "pass1_ms": round(p1_ms, 5), "pass1_GBps": round(p1_gbs, 1),
