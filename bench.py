@@ -314,6 +314,7 @@ def main():
         "batched": batched,
         "end_to_end": {
             "plain_ms": round(dt_plain * 1e3, 4), "bf16_ms": round(dt_bf16 * 1e3, 4),
+            "plain_rows_per_s": round(w.n / dt_plain), "bf16_rows_per_s": round(w.n / dt_bf16),
             "coreset_rows_plain": S_plain, "coreset_rows_bf16": S_bf16,
             "objective_plain": f_plain, "objective_bf16": f_bf16,
             "objective_all_rows_solve": ref,
