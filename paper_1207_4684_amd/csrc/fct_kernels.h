@@ -40,7 +40,15 @@ struct Pass1Plan {
 };
 
 hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStream_t st);
-size_t pass1_wave_lds(int r1, int c, int s);
+// Row stride (doubles) of the wave kernels' LDS accumulator for a slice of c
+// columns.  A lane group adds 4 adjacent columns of 16 random buckets; with a
+// stride that is a multiple of 4 the buckets' first columns fall on a few
+// banks (an FP64 LDS atomic measured 79 clocks at stride 8 against 27 at
+// stride 7), so even widths above 2 are padded by one column.
+__host__ __device__ inline int pass1_acc_stride(int c) { return (c > 2 && !(c & 1)) ? c + 1 : c; }
+// LDS bytes of the wave kernels: accumulator of r1 rows x `stride` doubles,
+// per-wave tables, and the exchange buffer for s > 256.
+size_t pass1_wave_lds(int r1, int stride, int s);
 int pass1_wave_rows_quantum();
 // whether the wave form for block size s reads the signs of D from the table
 // (s > 256) or draws them itself

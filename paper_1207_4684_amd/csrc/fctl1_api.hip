@@ -128,6 +128,8 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, 
     return p;
   }
   int cmax = (int)((budget - fixed) / per_col);
+  // the padded accumulator row (pass1_acc_stride) must fit too
+  while (cmax > 1 && (size_t)pass1_acc_stride(cmax) * per_col > budget - fixed) --cmax;
   if (cmax > q) cmax = q;
   // widest slices: every slice re-reads the random table and re-runs the
   // per-tile set-up, which costs more than the lanes a width that is not a
@@ -135,7 +137,7 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, 
   p.nslices = (q + cmax - 1) / cmax;
   p.c = (q + p.nslices - 1) / p.nslices;
   p.nslices = (q + p.c - 1) / p.c;
-  p.lds = pass1_wave_lds(r1, p.c, s);
+  p.lds = pass1_wave_lds(r1, pass1_acc_stride(p.c), s);
   int per_cu = (int)((size_t)(160 * 1024) / p.lds);
   if (per_cu < 1) per_cu = 1;
   const int64_t target = (int64_t)c->cus * per_cu * c->p1_waves_of_wgs;

@@ -12,7 +12,7 @@
 // adds: on gfx950 they sustain ~9x the rate of FP32 LDS atomic adds, and the
 // sums are FP64).  Its waves take 256-row tiles:
 //   1. the tile's table entries, 4 rows per lane (loaded one tile ahead), go
-//      to the wave's table in LDS as (bucket * c, Cauchy), shared by every
+//      to the wave's table in LDS as (bucket * stride, Cauchy), shared by every
 //      column;
 //   2. the slice's columns are processed 4 at a time, 16 lanes per column; a
 //      lane holds 16 rows {4L + i + 64k} of its column (float4 loads, the
@@ -176,10 +176,12 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
   const int c0 = blockIdx.y * a.c;
   const int cs = min(a.c, a.q - c0);
   double* acc = reinterpret_cast<double*>(smem_raw);
-  const size_t acc_bytes = (((size_t)a.r1 * a.c * sizeof(double)) + 15) & ~size_t(15);
+  const int stride = pass1_acc_stride(cs);  // accumulator row stride (see its definition)
+  const size_t acc_bytes =
+      (((size_t)a.r1 * pass1_acc_stride(a.c) * sizeof(double)) + 15) & ~size_t(15);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveLds& W = reinterpret_cast<WaveLds*>(smem_raw + acc_bytes)[wave];
-  for (int i = threadIdx.x; i < a.r1 * cs; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < a.r1 * stride; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
 
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_range;
@@ -214,7 +216,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
     }
     {
       // table entries of rows tile + 4 lane + {0, 1, 2, 3}; then the next tile's
-      const uint32_t ucs = (uint32_t)cs;  // the LDS table holds bucket * cs, the cell row offset
+      const uint32_t ucs = (uint32_t)stride;  // the LDS table holds bucket * stride, the row offset
       uint4* eh = reinterpret_cast<uint4*>(&W.entH[4 * lane]);
       uint4* ei = reinterpret_cast<uint4*>(&W.entI[4 * lane]);
       eh[0] = make_uint4(__umul24(tk.x & 0x7FFFu, ucs), __float_as_uint(tc0.x),
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
   float* part = reinterpret_cast<float*>(a.partials);
   for (int col = 0; col < cs; ++col) {
     float* dst = part + ((size_t)blockIdx.x * a.q + c0 + col) * a.r1;
-    for (int i = threadIdx.x; i < a.r1; i += blockDim.x) dst[i] = (float)acc[i * cs + col];
+    for (int i = threadIdx.x; i < a.r1; i += blockDim.x) dst[i] = (float)acc[i * stride + col];
   }
 }
 
@@ -307,11 +309,13 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
   const int c0 = blockIdx.y * a.c;
   const int cs = min(a.c, a.q - c0);
   double* acc = reinterpret_cast<double*>(smem_raw);
-  const size_t acc_bytes = (((size_t)a.r1 * a.c * sizeof(double)) + 15) & ~size_t(15);
+  const int stride = pass1_acc_stride(cs);  // accumulator row stride (see its definition)
+  const size_t acc_bytes =
+      (((size_t)a.r1 * pass1_acc_stride(a.c) * sizeof(double)) + 15) & ~size_t(15);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveLds& W = reinterpret_cast<WaveLds*>(smem_raw + acc_bytes)[wave];
   float* xch = reinterpret_cast<float*>(smem_raw + acc_bytes + kWaves * sizeof(WaveLds));
-  for (int i = threadIdx.x; i < a.r1 * cs; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < a.r1 * stride; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
 
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_range;
@@ -352,7 +356,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
     const bool more = it + 1 < niter && next < row1;  // this wave's next tile exists
     if (act) {
       // table entries of rows tile + 4 lane + {0, 1, 2, 3}; then the next tile's
-      const uint32_t ucs = (uint32_t)cs;  // the LDS table holds bucket * cs, the cell row offset
+      const uint32_t ucs = (uint32_t)stride;  // the LDS table holds bucket * stride, the row offset
       uint4* eh = reinterpret_cast<uint4*>(&W.entH[4 * lane]);
       uint4* ei = reinterpret_cast<uint4*>(&W.entI[4 * lane]);
       // I entries carry the sign of D(j) (bit 15 of the key) in bit 31
@@ -450,12 +454,12 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
   float* part = reinterpret_cast<float*>(a.partials);
   for (int col = 0; col < cs; ++col) {
     float* dst = part + ((size_t)blockIdx.x * a.q + c0 + col) * a.r1;
-    for (int i = threadIdx.x; i < a.r1; i += blockDim.x) dst[i] = (float)acc[i * cs + col];
+    for (int i = threadIdx.x; i < a.r1; i += blockDim.x) dst[i] = (float)acc[i * stride + col];
   }
 }
 
-size_t pass1_wave_lds(int r1, int c, int s) {
-  return ((((size_t)r1 * c * sizeof(double)) + 15) & ~size_t(15)) + kWaves * sizeof(WaveLds) +
+size_t pass1_wave_lds(int r1, int stride, int s) {
+  return ((((size_t)r1 * stride * sizeof(double)) + 15) & ~size_t(15)) + kWaves * sizeof(WaveLds) +
          (s > kTile ? (size_t)kWaves * kXch * sizeof(float) : 0);
 }
 
