@@ -43,12 +43,15 @@ namespace {
 
 constexpr int kTile = 256;
 constexpr int kWaves = 8;
-constexpr int kXch = 16 * 64;           // floats per wave in the cross-wave exchange (s > 256)
+constexpr int kXch = 8 * 64;            // floats per wave in the cross-wave exchange (s > 256):
+                                        // 8 of a lane's 16 values at a time
 constexpr int kSignRows = 4096;         // rows covered by one refresh of sign words (s <= 256)
 
-struct WaveLds {
-  uint2 entH[kTile];                    // {bucket * c, bits of 4 C / sqrt(s)} of the H-half copy
-  uint2 entI[kTile];                    // {bucket * c, bits of 4 C} of the I-half copy
+struct WaveTab {
+  uint2 entH[kTile];                    // {bucket * stride, bits of 4 C / sqrt(s)} of the H-half copy
+  uint2 entI[kTile];                    // {bucket * stride, bits of 4 C} of the I-half copy
+};
+struct WaveLds : WaveTab {
   uint32_t sgn[kSignRows / 32];         // sign words (s <= 256 form)
 };
 
@@ -313,8 +316,8 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
   const size_t acc_bytes =
       (((size_t)a.r1 * pass1_acc_stride(a.c) * sizeof(double)) + 15) & ~size_t(15);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WaveLds& W = reinterpret_cast<WaveLds*>(smem_raw + acc_bytes)[wave];
-  float* xch = reinterpret_cast<float*>(smem_raw + acc_bytes + kWaves * sizeof(WaveLds));
+  WaveTab& W = reinterpret_cast<WaveTab*>(smem_raw + acc_bytes)[wave];
+  float* xch = reinterpret_cast<float*>(smem_raw + acc_bytes + kWaves * sizeof(WaveTab));
   for (int i = threadIdx.x; i < a.r1 * stride; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
 
@@ -420,16 +423,19 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
         const int pw = wave ^ (1 << (bit - 8));
         const bool upper = (wave >> (bit - 8)) & 1;
         float* mine = xch + wave * kXch;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) mine[r * 64 + lane] = v[r];
-        __syncthreads();
         const float* theirs = xch + pw * kXch;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float o = theirs[r * 64 + lane];
-          v[r] = upper ? o - v[r] : v[r] + o;
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) mine[r * 64 + lane] = v[8 * h + r];
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const float o = theirs[r * 64 + lane];
+            v[8 * h + r] = upper ? o - v[8 * h + r] : v[8 * h + r] + o;
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
       // H-half copies: rows t = 4 L + i + 64 k, as for the I half
 #pragma unroll
@@ -459,8 +465,9 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
 }
 
 size_t pass1_wave_lds(int r1, int stride, int s) {
-  return ((((size_t)r1 * stride * sizeof(double)) + 15) & ~size_t(15)) + kWaves * sizeof(WaveLds) +
-         (s > kTile ? (size_t)kWaves * kXch * sizeof(float) : 0);
+  const size_t acc = (((size_t)r1 * stride * sizeof(double)) + 15) & ~size_t(15);
+  if (s > kTile) return acc + kWaves * (sizeof(WaveTab) + (size_t)kXch * sizeof(float));
+  return acc + kWaves * sizeof(WaveLds);
 }
 
 int pass1_wave_rows_quantum() { return kWaves * kTile; }
