@@ -8,9 +8,10 @@
 // positions), so the column slices below read it instead of drawing it again.
 //
 // A workgroup of 8 waves owns a range of rows and a slice of c columns of
-// X = [A, -b], with a private r1 x c FP64 accumulator in LDS (FP64 LDS atomic
-// adds: on gfx950 they sustain ~9x the rate of FP32 LDS atomic adds, and the
-// sums are FP64).  Its waves take 256-row tiles:
+// X = [A, -b], with a private FP64 accumulator in LDS of r1 rows at a stride
+// of pass1_acc_stride(c) doubles (FP64 LDS atomic adds: on gfx950 they
+// sustain ~9x the rate of FP32 LDS atomic adds, and the sums are FP64).  Its
+// waves take 256-row tiles:
 //   1. the tile's table entries, 4 rows per lane (loaded one tile ahead), go
 //      to the wave's table in LDS as (bucket * stride, Cauchy), shared by every
 //      column;
@@ -30,10 +31,11 @@
 // pass1_block_kernel (256 < s <= 2048): the workgroup walks its range in
 // steps of 8 tiles, wave w taking tile w, so a block spans s / 256
 // neighbouring waves; row bits 8-10 are the wave index and their butterflies
-// pair the waves through an LDS exchange buffer at workgroup barriers.  Its signs come with the
-// table (bit 15 of a row's key).  Either way the accumulator is written once
-// per workgroup and the partials are summed in a fixed order by the
-// reduction kernel.
+// pair the waves through an LDS exchange buffer (8 of a lane's 16 values at a
+// time) at workgroup barriers.  Its signs come with the table (bit 15 of a
+// row's key), so it keeps no sign words.  Either way the accumulator is
+// written once per workgroup and the partials are summed in a fixed order by
+// the reduction kernel.
 #include "fct_device.h"
 #include "fct_kernels.h"
 
