@@ -29,10 +29,15 @@
  *   - Random quantities come from Philox4x32-10 with key = seed and counters
  *     (index, 0, stream, 0) as listed in the design notes; the same seed gives
  *     the same Pi1, Pi2 and sampling decisions as the CPU oracle.
- *   - Floating-point sums inside a sketch are accumulated in LDS with atomic
- *     adds, so repeated runs agree to rounding, not bit for bit.  Integer and
- *     index outputs (RNG words, buckets, signs, selected rows given the same
- *     probabilities) are exact.
+ *   - Sketch sums of FP32 data with s <= 1024 and r1 <= 1024 are formed by one
+ *     lane each in an order fixed by the random streams, so repeated calls
+ *     give bitwise-identical Y, R, lambda, probabilities, coresets and
+ *     solutions.  Other shapes add into LDS atomically (FP64 data, s > 1024,
+ *     r1 > 1024) and repeated runs agree to rounding, unless the call sets
+ *     FCT_FLAG_DETERMINISTIC (FP32 data with s <= 1024; at r1 > 1024 the
+ *     buckets are split over ceil(r1 / 1024) workgroups, each streaming X
+ *     again).  Integer and index outputs (RNG words, buckets, signs, selected
+ *     rows given the same probabilities) are exact.
  */
 #ifndef FCTL1_H
 #define FCTL1_H
@@ -61,6 +66,8 @@ enum {
 
 /* Flags of fct_params.flags and of fct_sketch. */
 #define FCT_FLAG_NO_SIGN_FLIP 1u /* Pi1 without the random sign diagonal: the paper's Pi1 exactly */
+#define FCT_FLAG_DETERMINISTIC 2u /* bitwise-reproducible sketch at any r1 (FP32 data, s <= 1024;
+                                     FCT_ERR_BAD_ARG for other shapes)                        */
 
 typedef struct {
   int32_t s;      /* FWHT block size: power of two in [2, 4096]                  */
@@ -96,7 +103,7 @@ void *fct_stream(fct_ctx *ctx);
  *      only R is wanted.
  *   R: device, q x q column-major FP64, upper triangular with positive
  *      diagonal, Pi1 X = Q R (may be NULL).  Requires q <= 88.
- *   flags: FCT_FLAG_NO_SIGN_FLIP or 0.
+ *   flags: FCT_FLAG_NO_SIGN_FLIP, FCT_FLAG_DETERMINISTIC (see above) or 0.
  *   Conditions found on the device (a non-finite input, a rank-deficient
  *   sketch) are reported by the next fct_sync on the context (the call
  *   itself does not wait): FCT_ERR_NONFINITE, FCT_ERR_RANK_DEFICIENT.
@@ -255,6 +262,27 @@ int fct_fwht(fct_ctx *ctx, float *x, int64_t nblocks, int32_t s);
  * summed device milliseconds and the number of launches of `kind`. */
 int fct_profile(fct_ctx *ctx, int enable);
 int fct_profile_read(fct_ctx *ctx, int kind, double *total_ms, int64_t *count);
+
+/* Plan options of a context, for benchmarks and tests (the defaults need no
+ * call).  FCT_OPT_PASS1_KERNEL: FCT_P1_AUTO (default), FCT_P1_WAVE (the
+ * wave-level kernel with a random table), FCT_P1_OWNER (the bucket-owner
+ * kernel, FP32 with s <= 1024), FCT_P1_TILE (the workgroup-tile kernel); a
+ * choice that does not fit a shape falls back to the automatic one.
+ * FCT_OPT_PASS1_WGS_PER_CU: workgroups per CU the pass-1 grids aim for (>= 1).
+ * FCT_OPT_PASS1_TILE_THREADS: 256, 512 or 1024.  FCT_OPT_PASS2_WGS: cap of the
+ * FP32/BF16 pass-2 grid (0 = default).  FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS:
+ * workgroups of the coreset solve, or coreset rows per workgroup (0 =
+ * default).  Returns FCT_ERR_BAD_ARG for an unknown option or value. */
+enum {
+  FCT_OPT_PASS1_KERNEL = 1,
+  FCT_OPT_PASS1_WGS_PER_CU = 2,
+  FCT_OPT_PASS1_TILE_THREADS = 3,
+  FCT_OPT_PASS2_WGS = 4,
+  FCT_OPT_SOLVE_WGS = 5,
+  FCT_OPT_SOLVE_ROWS = 6
+};
+enum { FCT_P1_AUTO = 0, FCT_P1_WAVE = 1, FCT_P1_OWNER = 2, FCT_P1_TILE = 3 };
+int fct_set_option(fct_ctx *ctx, int option, int64_t value);
 
 /* BF16 copy (round to nearest even) of a device FP32 array. */
 int fct_to_bf16(fct_ctx *ctx, const float *x, int64_t count, uint16_t *y);

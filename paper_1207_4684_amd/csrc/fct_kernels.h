@@ -25,16 +25,21 @@ struct Pass1Args {
   void* partials;      // [nranges][q][r1] of the input type
   const uint4* tab_keys;  // wave kernel: per row, H bucket | sign of D(j) << 15 | I bucket << 16
   const float4* tab_c;    // wave kernel: per row, (4 C_H / sqrt(s), 4 C_I), two rows per float4
+  float scale_h;          // owner kernel: 4 / sqrt(s), the H-half factor
+  int32_t bucket_span;    // owner kernel: buckets per workgroup (<= 1024; grid z covers r1)
 };
 
 struct Pass1Plan {
-  int kind;            // 0: workgroup-tile kernel, 1: wave-level kernel (FP32, s <= 2048)
+  int kind;            // 0: workgroup-tile kernel, 1: wave-level kernel (FP32, s <= 2048),
+                       // 2: bucket-owner kernel (FP32, s <= 1024; deterministic)
   bool vec_ok;         // 16-byte aligned columns (wave kernel float4 loads)
   int threads;
   int rpt;             // rows per thread per chunk
   int c;
   int nslices;
   int nranges;
+  int nbranges;        // owner kernel: bucket ranges (grid z)
+  int bucket_span;     // owner kernel: buckets per range
   int64_t rows_per_range;
   size_t lds;
 };
@@ -59,6 +64,12 @@ int64_t pi1_table_rows(int64_t n_pad);
 hipError_t launch_pi1_table(uint64_t seed, uint32_t instance, int64_t row0g, int64_t rows, int s,
                             int r1, int sign_flip, uint4* keys, float4* cc, hipStream_t st);
 hipError_t launch_pass1_wave(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st);
+// Bucket-owner form (pass1_owner.hip): columns per slice for a bucket span,
+// its LDS bytes, the tile height (rows per workgroup step) and the launch.
+int pass1_owner_max_cols(int span);
+size_t pass1_owner_lds(int span, int c);
+int pass1_owner_tile_rows();
+hipError_t launch_pass1_owner(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st);
 hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
                                   double* Yd, int* flag, bool f64, hipStream_t st);
 hipError_t launch_rng_words(uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
@@ -100,8 +111,11 @@ struct Pass2Args {
   double* wg_sums;     // [grid]
 };
 enum Pass2Kind { kPass2F32 = 0, kPass2F64 = 1, kPass2BF16 = 2 };
-int pass2_grid(int64_t n, int kind);
-hipError_t launch_pass2(const Pass2Args& a, int kind, hipStream_t st);
+// grid of the pass-2 kernel of `kind` for n rows (cap_override > 0 caps the
+// MFMA forms' grid instead of the default); the caller sizes the per-workgroup
+// sums with the same value and passes it to launch_pass2.
+int pass2_grid(int64_t n, int kind, int cap_override = 0);
+hipError_t launch_pass2(const Pass2Args& a, int kind, int grid, hipStream_t st);
 hipError_t launch_sum_fixed(const double* parts, int count, double* out, hipStream_t st);
 
 // Selection: p_i = min(1, s_out lambda_i / sum), keep iff word_i < floor(p_i 2^32).
@@ -159,7 +173,7 @@ hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStre
 hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,
                        int64_t cap, int64_t S_hint, int d, int64_t ldat, bool f64, int iters,
                        double* work, double* x_out, double* obj_out, int* status,
-                       hipStream_t st);
+                       hipStream_t st, int rows_override = 0, int wgs_override = 0);
 
 hipError_t launch_to_bf16(const float* x, int64_t count, uint16_t* y, hipStream_t st);
 hipError_t launch_l1_objective(const void* A, const void* b, int64_t lda, int64_t n, int d,

@@ -30,11 +30,14 @@ struct fct_ctx {
   bool prof_on = false;
   int prof_n[3] = {0, 0, 0};
   hipEvent_t* prof_ev[3] = {nullptr, nullptr, nullptr};  // pairs (start, stop)
-  // pass-1 plan knobs
-  int p1_threads = 256;
+  // plan knobs (fct_set_option)
+  int p1_kernel = FCT_P1_AUTO;  // pass-1 kernel choice
+  int p1_threads = 256;         // workgroup-tile kernel threads
   size_t p1_lds_budget = 0;     // 0: the device's opt-in maximum
-  int p1_waves_of_wgs = 1;
-  int p1_force_tile = 0;        // 1: never use the wave-level pass-1 kernel
+  int p1_waves_of_wgs = 1;      // workgroups per CU the pass-1 grids aim for
+  int p2_wgs = 0;               // 0: default pass-2 grid cap
+  int irls_wgs = 0;             // 0: solver workgroups from the coreset size
+  int irls_rows = 0;            // 0: default coreset rows per solver workgroup
   // batched form: forked streams, events, staging and the cached graph
   static constexpr int kBranches = 4;
   hipStream_t branch[kBranches] = {};
@@ -153,9 +156,49 @@ Pass1Plan make_wave_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, 
   return p;
 }
 
+// Bucket-owner plan: grid (row ranges, column slices, bucket ranges).
+Pass1Plan make_owner_plan(const fct_ctx* c, int64_t n_pad, int q, int r1) {
+  Pass1Plan p{};
+  p.kind = 2;
+  p.threads = 512;
+  p.rpt = 1;
+  p.nbranges = (r1 + 1023) / 1024;
+  p.bucket_span = (r1 + p.nbranges - 1) / p.nbranges;
+  const int cmax = pass1_owner_max_cols(p.bucket_span);
+  p.nslices = (q + cmax - 1) / cmax;
+  p.c = (q + p.nslices - 1) / p.nslices;
+  p.nslices = (q + p.c - 1) / p.c;
+  p.lds = pass1_owner_lds(p.bucket_span, p.c);
+  const int64_t tile = pass1_owner_tile_rows();
+  const int64_t ntiles = (n_pad + tile - 1) / tile;
+  int64_t nranges = (int64_t)c->cus * c->p1_waves_of_wgs / ((int64_t)p.nslices * p.nbranges);
+  if (nranges < 1) nranges = 1;
+  if (nranges > ntiles) nranges = ntiles;
+  const int64_t tpr = (ntiles + nranges - 1) / nranges;
+  p.rows_per_range = tpr * tile;
+  p.nranges = (int)((ntiles + tpr - 1) / tpr);
+  return p;
+}
+
+// Pass-1 kernel for a sketch.  FP32 data with s <= 1024 takes the
+// bucket-owner kernel when r1 <= 1024 (one workgroup holds every bucket) or
+// when the caller asks for a deterministic sketch; other shapes take the
+// wave-level kernel (FP32, s <= 2048) or the workgroup-tile kernel, whose LDS
+// atomic adds make the sums reproducible to rounding only.  *err = 1: no
+// kernel fits; *err = 2: a deterministic sketch of this shape is not offered.
 Pass1Plan make_pass1_plan(const fct_ctx* c, int64_t n_pad, int q, int s, int r1, size_t es,
-                          int* err) {
-  if (es == sizeof(float) && s <= 2048 && r1 <= 32768 && !c->p1_force_tile) {
+                          uint32_t flags, int* err) {
+  *err = 0;
+  const bool owner_ok = es == sizeof(float) && s <= 1024;
+  const bool det = (flags & FCT_FLAG_DETERMINISTIC) != 0;
+  if (det && !owner_ok) {
+    *err = 2;
+    return Pass1Plan{};
+  }
+  if (owner_ok && (det || c->p1_kernel == FCT_P1_OWNER ||
+                   (c->p1_kernel == FCT_P1_AUTO && r1 <= 1024)))
+    return make_owner_plan(c, n_pad, q, r1);
+  if (es == sizeof(float) && s <= 2048 && r1 <= 32768 && c->p1_kernel != FCT_P1_TILE) {
     Pass1Plan w = make_wave_plan(c, n_pad, q, s, r1, err);
     if (!*err) return w;
   }
@@ -226,7 +269,7 @@ struct SketchBufs {
 
 template <typename C>
 void carve_sketch(C& cv, const Pass1Plan& p, int64_t n_pad, int q, int r1, size_t es, bool want_r) {
-  cv.template take<char>((size_t)p.nranges * q * r1 * es);
+  cv.template take<char>((size_t)p.nranges * q * r1 * (p.kind == 2 ? sizeof(float) : es));
   cv.template take<double>((size_t)r1 * q);
   if (p.kind == 1) {
     const int64_t rows = pi1_table_rows(n_pad);
@@ -242,7 +285,7 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   const int q = d + (b ? 1 : 0);
   const int64_t n_pad = (n + s - 1) / s * s;
   const size_t es = esize(dt);
-  void* partials = cv.take<char>((size_t)p.nranges * q * r1 * es);
+  void* partials = cv.take<char>((size_t)p.nranges * q * r1 * (p.kind == 2 ? sizeof(float) : es));
   double* Yd = cv.take<double>((size_t)r1 * q);
   uint4* tab_keys = nullptr;
   float4* tab_c = nullptr;
@@ -271,20 +314,24 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.partials = partials;
   a.tab_keys = tab_keys;
   a.tab_c = tab_c;
+  a.scale_h = 4.0f / sqrtf((float)s);
+  a.bucket_span = p.bucket_span;
+  const bool vec_ok = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0) &&
+                      (!b || (((uintptr_t)b & 15) == 0));
   prof_begin(c, 0);
-  if (p.kind == 1) {
+  if (p.kind == 2) {
+    HIP_TRY(launch_pass1_owner(a, p, vec_ok, c->stream));
+  } else if (p.kind == 1) {
     HIP_TRY(launch_pi1_table(seed, 0, row0g, pi1_table_rows(n_pad), s, r1,
                              pass1_wave_signs_in_table(s) ? a.sign_flip : 0, tab_keys, tab_c,
                              c->stream));
-    const bool vec_ok = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0) &&
-                        (!b || (((uintptr_t)b & 15) == 0));
     HIP_TRY(launch_pass1_wave(a, p, vec_ok, c->stream));
   } else {
     HIP_TRY(launch_pass1(a, p, dt == FCT_F64, c->stream));
   }
   prof_end(c, 0);
-  HIP_TRY(launch_reduce_partials(partials, p.nranges, r1, q, Y, Yd, c->flags + 0, dt == FCT_F64,
-                                 c->stream));
+  HIP_TRY(launch_reduce_partials(partials, p.nranges, r1, q, Y, Yd, c->flags + 0,
+                                 dt == FCT_F64 && p.kind != 2, c->stream));
   if (R) {
     double* work = cv.take<double>(qr_work_doubles(r1, q));
     const double rank_tol = dt == FCT_F64 ? 1e-13 : 1e-5;
@@ -324,7 +371,7 @@ int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, i
   float* Mfb = cv.take<float>((size_t)q * r2p);
   uint16_t* Mb = cv.take<uint16_t>((size_t)q * r2p);
   const int kind = dt == FCT_F64 ? kPass2F64 : (dt == FCT_BF16 ? kPass2BF16 : kPass2F32);
-  const int grid = pass2_grid(n, kind);
+  const int grid = pass2_grid(n, kind, c->p2_wgs);
   double* wg = cv.take<double>((size_t)grid);
   HIP_TRY(launch_form_m(R, q, r2, r2p, seed, 0, Md, Mf, Mfb, Mb, c->flags + 1, c->stream));
   Pass2Args a{};
@@ -340,20 +387,20 @@ int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, i
   a.lambda = lambda;
   a.wg_sums = wg;
   prof_begin(c, 1);
-  HIP_TRY(launch_pass2(a, kind, c->stream));
+  HIP_TRY(launch_pass2(a, kind, grid, c->stream));
   prof_end(c, 1);
   HIP_TRY(launch_sum_fixed(wg, grid, sum_lambda, c->stream));
   return FCT_OK;
 }
 
 template <typename C>
-void carve_probs(C& cv, int q, int r2, int64_t n, int kind) {
+void carve_probs(C& cv, const fct_ctx* c, int q, int r2, int64_t n, int kind) {
   const int r2p = r2_padded(r2);
   cv.template take<double>((size_t)q * r2p);
   cv.template take<float>((size_t)q * r2p);
   cv.template take<float>((size_t)q * r2p);
   cv.template take<uint16_t>((size_t)q * r2p);
-  cv.template take<double>((size_t)pass2_grid(n, kind));
+  cv.template take<double>((size_t)pass2_grid(n, kind, c->p2_wgs));
 }
 
 int run_select(fct_ctx* c, Carve& cv, const float* lambda, const double* sum_lambda, int64_t n,
@@ -416,12 +463,6 @@ int fct_create(fct_ctx** out, int device, void* hip_stream) {
   else if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
                hipSuccess && v > 0)
     c->lds_optin = (size_t)v;
-  if (const char* e = std::getenv("FCTL1_P1_THREADS")) c->p1_threads = std::atoi(e);
-  if (const char* e = std::getenv("FCTL1_P1_LDS_BUDGET")) c->p1_lds_budget = (size_t)std::atoll(e);
-  if (const char* e = std::getenv("FCTL1_P1_WAVES")) c->p1_waves_of_wgs = std::atoi(e);
-  if (const char* e = std::getenv("FCTL1_P1_KERNEL")) c->p1_force_tile = std::strcmp(e, "tile") == 0;
-  if (c->p1_threads != 256 && c->p1_threads != 512 && c->p1_threads != 1024) c->p1_threads = 256;
-  if (c->p1_waves_of_wgs < 1) c->p1_waves_of_wgs = 1;
   if (hipMalloc(&c->flags, 4 * sizeof(int)) != hipSuccess ||
       hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     fct_destroy(c);
@@ -477,6 +518,38 @@ int fct_sync(fct_ctx* c) {
 
 void* fct_stream(fct_ctx* c) { return c ? (void*)c->stream : nullptr; }
 
+int fct_set_option(fct_ctx* c, int option, int64_t value) {
+  if (!c) return FCT_ERR_BAD_ARG;
+  switch (option) {
+    case FCT_OPT_PASS1_KERNEL:
+      if (value < FCT_P1_AUTO || value > FCT_P1_TILE) return FCT_ERR_BAD_ARG;
+      c->p1_kernel = (int)value;
+      return FCT_OK;
+    case FCT_OPT_PASS1_WGS_PER_CU:
+      if (value < 1 || value > 64) return FCT_ERR_BAD_ARG;
+      c->p1_waves_of_wgs = (int)value;
+      return FCT_OK;
+    case FCT_OPT_PASS1_TILE_THREADS:
+      if (value != 256 && value != 512 && value != 1024) return FCT_ERR_BAD_ARG;
+      c->p1_threads = (int)value;
+      return FCT_OK;
+    case FCT_OPT_PASS2_WGS:
+      if (value < 0 || value > (1 << 20)) return FCT_ERR_BAD_ARG;
+      c->p2_wgs = (int)value;
+      return FCT_OK;
+    case FCT_OPT_SOLVE_WGS:
+      if (value < 0 || value > 64) return FCT_ERR_BAD_ARG;
+      c->irls_wgs = (int)value;
+      return FCT_OK;
+    case FCT_OPT_SOLVE_ROWS:
+      if (value < 0 || value > (1 << 20)) return FCT_ERR_BAD_ARG;
+      c->irls_rows = (int)value;
+      return FCT_OK;
+    default:
+      return FCT_ERR_BAD_ARG;
+  }
+}
+
 int fct_profile(fct_ctx* c, int enable) {
   if (!c) return FCT_ERR_BAD_ARG;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -516,7 +589,7 @@ int fct_sketch(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fct
   const int q = d + (b ? 1 : 0);
   const int64_t n_pad = (n + s - 1) / s * s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), &perr);
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   Measure m;
   carve_sketch(m, p, n_pad, q, r1, esize(dt), R != nullptr);
@@ -534,7 +607,7 @@ int fct_sketch_window(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t l
   const int q = d + (b ? 1 : 0);
   const int64_t n_pad = (n + s - 1) / s * s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), &perr);
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, r1, esize(dt), flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   Measure m;
   carve_sketch(m, p, n_pad, q, r1, esize(dt), false);
@@ -555,7 +628,7 @@ int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t
   Measure m;
   if (!lambda) m.take<float>((size_t)n);
   if (!sum_lambda) m.take<double>(1);
-  carve_probs(m, q, r2, n, kind);
+  carve_probs(m, c, q, r2, n, kind);
   if ((st = ensure_scratch(c, m.off))) return st;
   Carve cv(c->scratch);
   float* lam = lambda ? lambda : cv.take<float>((size_t)n);
@@ -580,7 +653,7 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
   const int q = d + 1;
   const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), &perr);
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   double* R = cv.take<double>((size_t)q * q);
   float* lam = cv.take<float>((size_t)n);
@@ -616,7 +689,7 @@ static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype 
   const int q = d + 1;
   const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), &perr);
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);
   Measure m;
   m.take<double>((size_t)q * q);
   m.take<float>((size_t)n);
@@ -624,7 +697,7 @@ static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype 
   const size_t base = m.off;
   Measure a, bb, cc;
   carve_sketch(a, p, n_pad, q, prm->r1, esize(dt), true);
-  carve_probs(bb, q, prm->r2, n, lowp ? kPass2BF16 : (dt == FCT_F64 ? kPass2F64 : kPass2F32));
+  carve_probs(bb, c, q, prm->r2, n, lowp ? kPass2BF16 : (dt == FCT_F64 ? kPass2F64 : kPass2F32));
   carve_select(cc, n);
   size_t mx = a.off;
   if (bb.off > mx) mx = bb.off;
@@ -705,7 +778,7 @@ int l1_solve(fct_ctx* c, const void* At, const void* bt, const double* w, int64_
                          c->stream));
   prof_begin(c, 2);
   HIP_TRY(launch_irls(At, bt, w, S_dev, S, S, d, ldat, dt == FCT_F64, iters, work, outv,
-                      outv + 64, c->flags + 1, c->stream));
+                      outv + 64, c->flags + 1, c->stream, c->irls_rows, c->irls_wgs));
   prof_end(c, 2);
   HIP_TRY(hipMemcpyAsync(c->pinned, outv, 65 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   const int fl = read_flags(c);
@@ -759,7 +832,7 @@ int l1_regress(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, i
     prof_begin(c, 2);
     const int64_t S_hint = prm.s_out < cap ? prm.s_out : cap;
     HIP_TRY(launch_irls(At, bt, w, S_dev, cap, S_hint, d, cap, dt == FCT_F64, iters, work, outv,
-                        outv + 64, c->flags + 1, c->stream));
+                        outv + 64, c->flags + 1, c->stream, c->irls_rows, c->irls_wgs));
     prof_end(c, 2);
     HIP_TRY(hipMemcpyAsync(c->pinned, outv, 65 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync((char*)c->pinned + 1024, S_dev, sizeof(int64_t), hipMemcpyDeviceToHost,
@@ -831,7 +904,7 @@ int time_sketch(fct_ctx* c, const fct_instance& in, fct_dtype dt, int s, float* 
   const int q = in.d + 1;
   const int64_t n_pad = (in.n + s - 1) / s * s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, in.prm.r1, esize(dt), &perr);
+  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, in.prm.r1, esize(dt), in.prm.flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   Measure m;
   carve_sketch(m, p, n_pad, q, in.prm.r1, esize(dt), false);

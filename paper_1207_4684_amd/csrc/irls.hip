@@ -605,16 +605,14 @@ hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStre
   return hipGetLastError();
 }
 
-static int irls_row_target() {
-  int r = kIrlsRowTarget;
-  if (const char* e = std::getenv("FCTL1_IRLS_ROWS")) r = std::atoi(e);
+static int irls_row_target(int rows_override) {
+  const int r = rows_override > 0 ? rows_override : kIrlsRowTarget;
   return r < 16 ? 16 : r;
 }
 
-static int irls_workgroups(int64_t S_hint) {
-  const int rt = irls_row_target();
-  int64_t p = (S_hint + rt - 1) / rt;
-  if (const char* e = std::getenv("FCTL1_IRLS_WGS")) p = std::atoi(e);
+static int irls_workgroups(int64_t S_hint, int rows_override, int wgs_override) {
+  const int rt = irls_row_target(rows_override);
+  int64_t p = wgs_override > 0 ? wgs_override : (S_hint + rt - 1) / rt;
   if (p < 1) p = 1;
   if (p > kIrlsMaxWgs) p = kIrlsMaxWgs;
   return (int)p;
@@ -623,10 +621,10 @@ static int irls_workgroups(int64_t S_hint) {
 hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,
                        int64_t cap, int64_t S_hint, int d, int64_t ldat, bool f64, int iters,
                        double* work, double* x_out, double* obj_out, int* status,
-                       hipStream_t st) {
+                       hipStream_t st, int rows_override, int wgs_override) {
   if (d > kIrlsMaxD || d < 1) return hipErrorInvalidValue;
   const IrlsGeom g(d, f64 ? sizeof(double) : sizeof(float));
-  const int P = irls_workgroups(S_hint);
+  const int P = irls_workgroups(S_hint, rows_override, wgs_override);
   IrlsArgs a;
   a.At = At;
   a.bt = bt;
@@ -636,7 +634,7 @@ hipError_t launch_irls(const void* At, const void* bt, const double* w, const in
   a.ldat = ldat;
   a.d = d;
   a.iters = iters;
-  a.row_target = irls_row_target();
+  a.row_target = irls_row_target(rows_override);
   a.part = work;
   a.bar = reinterpret_cast<unsigned*>(work + irls_work_doubles(0, d) - 8);
   a.x_out = x_out;

@@ -38,6 +38,7 @@
 // the reduction kernel.
 #include "fct_device.h"
 #include "fct_kernels.h"
+#include "wave_fwht.h"
 
 namespace fctl1 {
 
@@ -56,59 +57,6 @@ struct WaveTab {
 struct WaveLds : WaveTab {
   uint32_t sgn[kSignRows / 32];         // sign words (s <= 256 form)
 };
-
-// v of the lane whose L differs in bit B (L = lane % 16: DPP within a row of
-// 16 lanes).  Bit 0: quad_perm [1,0,3,2]; bit 1: quad_perm [2,3,0,1]; bit 2:
-// row_half_mirror (L ^ 7) then quad_perm [3,2,1,0] (^ 3); bit 3: row_ror:8.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int B>
-__device__ __forceinline__ float lane_xor(float v) {
-  if constexpr (B == 0) return dpp_f<0xB1>(v);
-  else if constexpr (B == 1) return dpp_f<0x4E>(v);
-  else if constexpr (B == 2) return dpp_f<0x1B>(dpp_f<0x141>(v));
-  else return dpp_f<0x128>(v);
-}
-
-// butterflies along bit B of L (row bit 2 + B): the lower lane keeps x + y,
-// the upper one x - y, as p + (+-1) v with one rounding, like x + y and x - y
-template <int B>
-__device__ __forceinline__ void lane_stage(float (&v)[16], int L) {
-  const float sg = ((L >> B) & 1) ? -1.0f : 1.0f;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const float p = lane_xor<B>(v[r]);
-    v[r] = fmaf(sg, v[r], p);
-  }
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void bfly(float& a, float& b) {
-  const float x = a, y = b;
-  a = x + y;
-  b = x - y;
-}
-
-// butterflies along register-index bit `rb` (0..3) of a 16-value vector
-__device__ __forceinline__ void reg_stage(float (&v)[16], int rb) {
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    if (!((r >> rb) & 1)) {
-      switch (rb) {
-        case 0: bfly(v[r], v[r + 1]); break;
-        case 1: bfly(v[r], v[r + 2]); break;
-        case 2: bfly(v[r], v[r + 4]); break;
-        default: bfly(v[r], v[r + 8]); break;
-      }
-    }
-}
 
 __device__ __forceinline__ void load_group(const Pass1Args& a, int c0, int cs, int64_t tile,
                                            int grp, int g, int L, bool vec_ok, float (&v)[16]) {

@@ -349,12 +349,10 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
   if (threadIdx.x == 0) a.wg_sums[blockIdx.x] = s;
 }
 
-int pass2_grid(int64_t n, int kind) {
+int pass2_grid(int64_t n, int kind, int cap_override) {
   if (kind != kPass2F64) {
     // MFMA forms: 64-row tiles per wave, grid-stride over the tiles
-    int64_t cap = 1024;
-    if (const char* e = std::getenv("FCTL1_P2_WGS")) cap = std::atoll(e);
-    if (cap < 1) cap = 1;
+    int64_t cap = cap_override > 0 ? cap_override : 1024;
     int64_t want = (n + 255) / 256;
     if (want > cap) want = cap;
     return (int)(want < 1 ? 1 : want);
@@ -365,8 +363,7 @@ int pass2_grid(int64_t n, int kind) {
 }
 
 template <typename TX>
-static hipError_t launch_pass2_t(const Pass2Args& a, int r2p, hipStream_t st) {
-  const int grid = pass2_grid(a.n, 0);
+static hipError_t launch_pass2_t(const Pass2Args& a, int r2p, int grid, hipStream_t st) {
   switch (r2p) {
     case 4: hipLaunchKernelGGL((pass2_valu_kernel<TX, 4>), dim3(grid), dim3(kP2Threads), 0, st, a); break;
     case 8: hipLaunchKernelGGL((pass2_valu_kernel<TX, 8>), dim3(grid), dim3(kP2Threads), 0, st, a); break;
@@ -378,11 +375,11 @@ static hipError_t launch_pass2_t(const Pass2Args& a, int r2p, hipStream_t st) {
 }
 
 
-hipError_t launch_pass2(const Pass2Args& a, int kind, hipStream_t st) {
+hipError_t launch_pass2(const Pass2Args& a, int kind, int grid, hipStream_t st) {
   const int r2p = r2_padded(a.r2);
-  if (kind == kPass2F64) return launch_pass2_t<double>(a, r2p, st);
+  if (grid < 1) return hipErrorInvalidValue;
+  if (kind == kPass2F64) return launch_pass2_t<double>(a, r2p, grid, st);
   if (a.q > 65 || a.r2 > 32) return hipErrorInvalidValue;
-  const int grid = pass2_grid(a.n, kind);
   if (kind == kPass2BF16) {
     const int ks = (a.q + 15) >> 4;
 #define P2_BF16(MT, KS) hipLaunchKernelGGL((pass2_mfma_bf16_kernel<MT, KS>), dim3(grid), dim3(kP2Threads), 0, st, a)

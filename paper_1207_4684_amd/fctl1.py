@@ -19,6 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libfctl1.so")
 
 FCT_F32, FCT_F64, FCT_BF16 = 0, 1, 2
 FCT_FLAG_NO_SIGN_FLIP = 1
+FCT_FLAG_DETERMINISTIC = 2
+FCT_OPT_PASS1_KERNEL, FCT_OPT_PASS1_WGS_PER_CU, FCT_OPT_PASS1_TILE_THREADS = 1, 2, 3
+FCT_OPT_PASS2_WGS, FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS = 4, 5, 6
+FCT_P1_AUTO, FCT_P1_WAVE, FCT_P1_OWNER, FCT_P1_TILE = 0, 1, 2, 3
 STATUS = {0: "ok", -1: "bad argument", -2: "out of device memory", -3: "non-finite value in input",
           -4: "rank deficient", -5: "HIP runtime error", -6: "coreset larger than capacity"}
 
@@ -76,6 +80,7 @@ def _load():
                                               PD, PD, PI64, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)]),
         "fct_profile": (ctypes.c_int, [P, ctypes.c_int]),
+        "fct_set_option": (ctypes.c_int, [P, ctypes.c_int, I64]),
         "fct_profile_read": (ctypes.c_int, [P, ctypes.c_int, PD, PI64]),
     }
     for name, (res, args) in sig.items():
@@ -90,7 +95,7 @@ EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream
             "fct_sketch_window",
             "l1_sample_probs", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
             "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
-            "fct_profile", "fct_profile_read", "l1_regress_batched")
+            "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option")
 
 
 def _check(st: int, where: str):
@@ -151,6 +156,10 @@ class Context:
 
     def sync(self):
         _check(_lib.fct_sync(self.handle), "fct_sync")
+
+    def set_option(self, option: int, value: int):
+        """fct_set_option: plan options (pass-1 kernel, grid sizes)."""
+        _check(_lib.fct_set_option(self.handle, option, int(value)), "fct_set_option")
 
     def profile(self, enable: bool):
         _check(_lib.fct_profile(self.handle, 1 if enable else 0), "fct_profile")
