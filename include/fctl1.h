@@ -66,6 +66,8 @@ enum {
 
 /* Flags of fct_params.flags and of fct_sketch. */
 #define FCT_FLAG_NO_SIGN_FLIP 1u /* Pi1 without the random sign diagonal: the paper's Pi1 exactly */
+#define FCT_FLAG_GAUSSIAN_PI2 4u /* optimized regression: Pi2 of standard Gaussians (figure
+                                    OptimizedFastCauchyRegression), see l1_sample_probs_ex */
 #define FCT_FLAG_DETERMINISTIC 2u /* bitwise-reproducible sketch at any r1 (FP32 data, s <= 1024;
                                      FCT_ERR_BAD_ARG for other shapes)                        */
 
@@ -146,6 +148,24 @@ int fct_sketch_window(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t
 int l1_sample_probs(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
                     int64_t lda, fct_dtype dt, const double *R, int32_t r2, uint64_t seed,
                     int64_t s_out, float *lambda, float *p, double *sum_lambda);
+
+/*
+ * l1_sample_probs_ex: l1_sample_probs with flags.  FCT_FLAG_GAUSSIAN_PI2
+ * takes Pi2 of independent standard Gaussians (the optimized regression
+ * figure, OptimizedFastCauchyRegression, step 4; Box-Muller from words 0 and 1
+ * of stream-2 call a * r2 + c) instead of Cauchys: (U Pi2)_ij is then
+ * N(0, ||U_(i)||_2^2) and lambda_i estimates 0.674 ||U_(i)||_2, an l2 row norm
+ * within sqrt(q) of the l1 one; fewer columns r2 suffice.  The probabilities
+ * are normalized as in the main figure (p_i = min{1, s_out lambda_i / sum
+ * lambda}): the optimized figure prints p_i = min{1, s lambda_i} without the
+ * sum, while its proof normalizes.  Other flags are ignored.  Other
+ * arguments as l1_sample_probs.  fct_params.flags carries the same flag to
+ * l1_coreset, l1_regress and l1_regress_batched.
+ */
+int l1_sample_probs_ex(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
+                       int64_t lda, fct_dtype dt, const double *R, int32_t r2, uint64_t seed,
+                       int64_t s_out, uint32_t flags, float *lambda, float *p,
+                       double *sum_lambda);
 
 /*
  * l1_coreset: steps 1-7.  Row i is kept iff its stream-3 word is below

@@ -3,7 +3,8 @@
 FastL1Basis figure: compute Pi1 A and its QR factorization Pi1 A = Q R; the
 basis is U = A R^-1 (never formed here).  FastCauchyRegression figure, steps
 2-4: the same with X = [A, -b]; Pi2 in R^{q x r2} is a matrix of independent
-Cauchys and Lambda = U Pi2 = X (R^-1 Pi2).  The running-time paragraph of the
+Cauchys and Lambda = U Pi2 = X (R^-1 Pi2).  The optimized regression figure
+(OptimizedFastCauchyRegression) takes Pi2 Gaussian instead.  The running-time paragraph of the
 regression proof computes R^-1 Pi2 first and then X (R^-1 Pi2); so does this
 build.
 
@@ -38,8 +39,18 @@ def qr_r(Y) -> np.ndarray:
     return R
 
 
-def m_matrix(R, seed: int, r2: int, instance: int = 0) -> np.ndarray:
-    """M = R^-1 Pi2 (q x r2), by a triangular solve R M = Pi2."""
+def m_matrix(R, seed: int, r2: int, instance: int = 0, pi2: str = "cauchy") -> np.ndarray:
+    """M = R^-1 Pi2 (q x r2), by a triangular solve R M = Pi2.
+
+    pi2 = "cauchy": independent Cauchys (FastCauchyRegression figure, step 3);
+    pi2 = "gaussian": independent standard Gaussians (the optimized
+    regression figure, step 4), whose (U Pi2)_ij are N(0, ||U_(i)||_2^2).
+    """
     R = np.asarray(R, dtype=np.float64)
-    pi2 = philox.pi2_matrix(seed, R.shape[0], r2, instance)
-    return scipy.linalg.solve_triangular(R, pi2, lower=False)
+    if pi2 == "cauchy":
+        P = philox.pi2_matrix(seed, R.shape[0], r2, instance)
+    elif pi2 == "gaussian":
+        P = philox.pi2_gaussian_matrix(seed, R.shape[0], r2, instance)
+    else:
+        raise ValueError(pi2)
+    return scipy.linalg.solve_triangular(R, P, lower=False)

@@ -25,7 +25,9 @@ written description): key = (seed mod 2^32, seed >> 32); counter =
   2 s beta + s + t (I-half).  Bucket = floor(w * r1 / 2^32).
 * stream 1, idx = j >> 7: bit (j & 31) of word (j >> 5) & 3 gives the sign
   D(j) = 1 - 2*bit.
-* stream 2, idx = a * r2 + c: word w0 gives the Cauchy Pi2[a, c].
+* stream 2, idx = a * r2 + c: word w0 gives the Cauchy Pi2[a, c]; for the
+  optimized regression (Gaussian Pi2) words (w0, w1) give the Gaussian
+  Pi2[a, c] by the Box-Muller transform.
 * stream 3, idx = i >> 2: word (i & 3) is the uniform that decides row i.
 
 Pinned by ``tests/test_oracle_rng.py`` against an independent implementation
@@ -147,6 +149,28 @@ def pi2_matrix(seed: int, q: int, r2: int, instance: int = 0):
     idx = np.arange(q * r2, dtype=np.uint64)
     w0 = stream_words(seed, STREAM_PI2, idx, instance)[0]
     return cauchy_from_word(w0).reshape(q, r2)
+
+
+def gaussian_from_words(w0, w1):
+    """Standard Gaussian variate from two 32-bit words, in FP64.
+
+    Box and Muller (1958): for independent uniforms u1, u2 in (0, 1),
+    sqrt(-2 ln u1) cos(2 pi u2) is standard normal (the pair (R, Theta) with
+    R^2 = -2 ln u1 exponential of mean 2 and Theta uniform is the polar form of
+    two independent standard normals).  Here u = (w + 1/2) / 2^32, so u1 is
+    never 0 or 1.
+    """
+    u1 = (np.asarray(w0, dtype=np.float64) + 0.5) / 4294967296.0
+    u2 = (np.asarray(w1, dtype=np.float64) + 0.5) / 4294967296.0
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def pi2_gaussian_matrix(seed: int, q: int, r2: int, instance: int = 0):
+    """Pi2 in R^{q x r2}, independent standard Gaussians (stream 2, words 0
+    and 1): the optimized regression figure's step 4."""
+    idx = np.arange(q * r2, dtype=np.uint64)
+    w = stream_words(seed, STREAM_PI2, idx, instance)
+    return gaussian_from_words(w[0], w[1]).reshape(q, r2)
 
 
 def sample_words(seed: int, n: int, instance: int = 0, start: int = 0):

@@ -28,12 +28,19 @@ def form_x(A, b=None) -> np.ndarray:
 
 
 def l1_regress(A, b, s: int, r1: int, r2: int, s_out: float, seed: int,
-               sign_flip: bool = True, lowp_pass2: bool = False, solve: bool = True):
-    """Run steps 1-8; return every intermediate in a dict."""
+               sign_flip: bool = True, lowp_pass2: bool = False, solve: bool = True,
+               pi2: str = "cauchy"):
+    """Run steps 1-8; return every intermediate in a dict.
+
+    pi2 = "gaussian" runs the optimized regression figure instead: Pi2 of
+    independent Gaussians, the same median estimate and the probabilities
+    normalized by the sum of the estimates (the figure's p_i = min{1, s
+    lambda_i} omits the sum; its proof normalizes, and so does this reading).
+    """
     X = form_x(A, b)
     Y = fct.pi1_apply(X, s, r1, seed, sign_flip=sign_flip)
     R = basis.qr_r(Y)
-    M = basis.m_matrix(R, seed, r2)
+    M = basis.m_matrix(R, seed, r2, pi2=pi2)
     if lowp_pass2:
         Xl = lowp.round_bf16(np.asarray(X, dtype=np.float32))
         Ml = lowp.round_bf16(np.asarray(M, dtype=np.float32))

@@ -11,7 +11,8 @@
 //             block b = j / s sits at k = 2 s b + (j mod s) (H-half) and
 //             k + s (I-half);
 //   stream 1: idx = j >> 7, bit j & 31 of word (j >> 5) & 3 -> sign D(j);
-//   stream 2: idx = a * r2 + c, word 0 -> Pi2[a][c];
+//   stream 2: idx = a * r2 + c, word 0 -> Cauchy Pi2[a][c] (words 0 and 1 ->
+//             Gaussian Pi2[a][c] for the optimized regression);
 //   stream 3: idx = i >> 2, word i & 3 -> uniform deciding row i.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -21,13 +22,18 @@ namespace fctl1 {
 
 enum : uint32_t { kStreamPi1 = 0, kStreamSign = 1, kStreamPi2 = 2, kStreamSample = 3 };
 
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96: odd parity of the inputs)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                   xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -55,7 +61,8 @@ __device__ __forceinline__ uint32_t bucket_from_word(uint32_t w, uint32_t r1) {
 // integers.  sin and cos come from their Taylor series in x^2 (terms to x^9
 // and x^10: truncation below 2e-9 relative on (0, pi/4]); the argument is
 // formed from an exact 22-bit/8-bit split of the integer numerator and a
-// two-term FP32 split of pi 2^-32.
+// two-term FP32 split of pi 2^-32; the quotient takes the hardware reciprocal
+// refined by one Newton step.
 __device__ __forceinline__ float cauchy_from_word(uint32_t w) {
   const bool neg = w < 0x80000000u;
   const uint32_t m = neg ? w : ~w;                   // < 2^31
@@ -77,8 +84,11 @@ __device__ __forceinline__ float cauchy_from_word(uint32_t w) {
   cs = fmaf(x2, cs, -0.5f);
   cs = fmaf(x2, cs, 1.0f);
   const float num = lower ? cs : sn;
-  const float den = lower ? sn : cs;
-  const float c = num * __frcp_rn(den);
+  const float den = lower ? sn : cs;  // in [3.6e-10, 1]: normal, no overflow
+  // reciprocal: v_rcp_f32 (about 1 ulp) and one Newton step r (2 - den r)
+  float rr = __builtin_amdgcn_rcpf(den);
+  rr = fmaf(fmaf(-den, rr, 1.0f), rr, rr);
+  const float c = num * rr;
   return neg ? -c : c;
 }
 
@@ -89,6 +99,15 @@ __device__ __forceinline__ double cauchy_from_word_f64(uint32_t w) {
   const double v = ((double)m + 0.5) * 0x1p-32;
   const double c = 1.0 / tan(3.141592653589793 * v);
   return neg ? -c : c;
+}
+
+// FP64 standard Gaussian for the optimized regression's Pi2, from two words
+// of one stream-2 call by the Box-Muller transform: with u = (w + 1/2) / 2^32,
+// sqrt(-2 ln u1) cos(2 pi u2) is N(0, 1) for independent uniforms u1, u2.
+__device__ __forceinline__ double gaussian_from_words_f64(uint32_t w0, uint32_t w1) {
+  const double u1 = ((double)w0 + 0.5) * 0x1p-32;
+  const double u2 = ((double)w1 + 0.5) * 0x1p-32;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
 
 // Stacked position of the H-half copy of padded row j (the I-half is + s).

@@ -90,9 +90,10 @@ hipError_t launch_qr(const double* Y, int r1, int q, double* work, double* R, do
 // M = R^-1 Pi2 (q x r2), written row-major with row stride ldm >= r2 (zero
 // padding) as FP64, and when non-NULL as FP32 (Mf), as FP32 values of its
 // BF16 rounding (Mfb) and as BF16 bit patterns (Mb).
+// gaussian: Pi2 of standard Gaussians (optimized regression) instead of Cauchys.
 hipError_t launch_form_m(const double* R, int q, int r2, int ldm, uint64_t seed,
                          uint32_t instance, double* Md, float* Mf, float* Mfb, uint16_t* Mb,
-                         int* status, hipStream_t st);
+                         int* status, hipStream_t st, bool gaussian = false);
 __host__ __device__ int r2_padded(int r2);
 
 // Pass 2: lambda and per-workgroup FP64 partial sums of lambda.

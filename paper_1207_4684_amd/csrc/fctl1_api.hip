@@ -363,7 +363,7 @@ struct ProbBufs {
 
 int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, int32_t d,
               int64_t lda, fct_dtype dt, const double* R, int32_t r2, uint64_t seed,
-              float* lambda, double* sum_lambda) {
+              float* lambda, double* sum_lambda, uint32_t flags) {
   const int q = d + (xb ? 1 : 0);
   const int r2p = r2_padded(r2);
   double* Md = cv.take<double>((size_t)q * r2p);
@@ -373,7 +373,8 @@ int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, i
   const int kind = dt == FCT_F64 ? kPass2F64 : (dt == FCT_BF16 ? kPass2BF16 : kPass2F32);
   const int grid = pass2_grid(n, kind, c->p2_wgs);
   double* wg = cv.take<double>((size_t)grid);
-  HIP_TRY(launch_form_m(R, q, r2, r2p, seed, 0, Md, Mf, Mfb, Mb, c->flags + 1, c->stream));
+  HIP_TRY(launch_form_m(R, q, r2, r2p, seed, 0, Md, Mf, Mfb, Mb, c->flags + 1, c->stream,
+                        (flags & FCT_FLAG_GAUSSIAN_PI2) != 0));
   Pass2Args a{};
   a.A = X;
   a.b = xb;
@@ -616,9 +617,9 @@ int fct_sketch_window(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t l
   return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, nullptr, nullptr, p, row0);
 }
 
-int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
-                    fct_dtype dt, const double* R, int32_t r2, uint64_t seed, int64_t s_out,
-                    float* lambda, float* p, double* sum_lambda) {
+int l1_sample_probs_ex(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d,
+                       int64_t lda, fct_dtype dt, const double* R, int32_t r2, uint64_t seed,
+                       int64_t s_out, uint32_t flags, float* lambda, float* p, double* sum_lambda) {
   int st = check_common(c, A, n, d, lda);
   if (st) return st;
   if (dt != FCT_F32 && dt != FCT_F64 && dt != FCT_BF16) return FCT_ERR_BAD_ARG;
@@ -633,7 +634,7 @@ int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t
   Carve cv(c->scratch);
   float* lam = lambda ? lambda : cv.take<float>((size_t)n);
   double* sl = sum_lambda ? sum_lambda : cv.take<double>(1);
-  if ((st = run_probs(c, cv, A, b, n, d, lda, dt, R, r2, seed, lam, sl))) return st;
+  if ((st = run_probs(c, cv, A, b, n, d, lda, dt, R, r2, seed, lam, sl, flags))) return st;
   if (p) {
     SelectArgs a{};
     a.lambda = lam;
@@ -644,6 +645,13 @@ int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t
     HIP_TRY(launch_probs_only(a, c->stream));
   }
   return FCT_OK;
+}
+
+int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+                    fct_dtype dt, const double* R, int32_t r2, uint64_t seed, int64_t s_out,
+                    float* lambda, float* p, double* sum_lambda) {
+  return l1_sample_probs_ex(c, A, b, n, d, lda, dt, R, r2, seed, s_out, 0u, lambda, p,
+                            sum_lambda);
 }
 
 static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d,
@@ -671,7 +679,7 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
     sub.off = cv.off;
     const bool lowp = A_lowp != nullptr;
     if ((st = run_probs(c, sub, lowp ? A_lowp : A, lowp ? b_lowp : b, n, d, lowp ? ld_lowp : lda,
-                        lowp ? FCT_BF16 : dt, R, prm->r2, prm->seed, lam, sl)))
+                        lowp ? FCT_BF16 : dt, R, prm->r2, prm->seed, lam, sl, prm->flags)))
       return st;
   }
   {

@@ -4,7 +4,7 @@
 // position).
 //
 // A workgroup of 8 waves owns a range of whole 8192-row tiles, a slice of at
-// most kOwnColsMax columns of X = [A, -b] and a range of at most 1024 buckets
+// most 18 (24) columns of X = [A, -b] and a range of at most 1024 (512) buckets
 // (rows of Y).  Lane t owns one or two of those buckets.  Per tile:
 //   1. each wave draws the random part of Pi1 for its 1024 rows: D(j) for
 //      every row, and bucket and Cauchy of both stacked copies of every row,
@@ -22,9 +22,12 @@
 //      copy into its slot, runs the butterflies, and stores
 //      4 C_k (H u) / sqrt(s) of each H-half copy into its slot; after a barrier
 //      lane t sums its buckets' segments in slot order (FP32 when a bucket
-//      takes at most about 64 positions of a tile, FP64 otherwise) and parks
-//      the sums in LDS;
-//   4. at the end of the tile lane t adds the parked sums into FP64 registers.
+//      takes at most about 64 positions of a tile, FP64 otherwise) and adds
+//      the sums into its FP64 accumulators for that column (registers).
+//      Columns alternate between two staging arrays, so one barrier per
+//      column separates writers and readers, and half of the waves sum a
+//      column before producing the next one while the other half produce
+//      first, which overlaps sums and butterflies on every SIMD.
 // Nothing is added atomically to a sum: every sum is formed by one lane in an
 // order fixed by the random streams, so the sketch is the same bit for bit on
 // every run.  The FP64 accumulators are written once per workgroup as FP32
@@ -44,29 +47,30 @@ constexpr int kORowsWave = 1024;         // rows per wave per tile
 constexpr int kOTile = kOW * kORowsWave; // rows per tile
 constexpr int kOPos = 2 * kOTile;        // stacked positions per tile
 constexpr int kOColsNB2 = 18;            // columns per slice when a lane owns two buckets
-constexpr int kOColsNB1 = 32;            // ... one bucket
+constexpr int kOColsNB1 = 24;            // ... one bucket
 
 struct OwnLayout {
-  uint32_t stage, cnt, tsum, sgn, wsum, total;
+  uint32_t stage, stage_bytes, cnt, sgn, wsum, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t v) { return (v + 15u) & ~15u; }
 
-// LDS carve for `span` buckets and `c` columns: the bucket-sorted staging
-// array (every segment padded to even length, plus a discard slot), per-wave
-// counters (two 16-bit counters per word when a lane owns two buckets), the
-// parked per-column sums, per-wave sign words and the scan's wave totals.
-__host__ __device__ inline OwnLayout own_layout(int span, int c) {
+// LDS carve for `span` buckets: two bucket-sorted staging arrays (columns
+// alternate between them; every segment padded to even length, plus a
+// discard slot), per-wave counters (two 16-bit counters
+// per word when a lane owns two buckets, plus a spare word for positions
+// outside the workgroup's bucket range), per-wave sign words and the scan's
+// wave totals.
+__host__ __device__ inline OwnLayout own_layout(int span) {
   const int nb = span > 512 ? 2 : 1;
   const int cw = nb == 2 ? (span + 1) / 2 : span;
   OwnLayout L;
   uint32_t o = 0;
   L.stage = o;
-  o += al16((uint32_t)(kOPos + span + 4) * 4u);
+  L.stage_bytes = al16((uint32_t)(kOPos + span + 4) * 4u);
+  o += 2 * L.stage_bytes;
   L.cnt = o;
-  o += al16((uint32_t)(kOW * cw) * 4u);
-  L.tsum = o;
-  o += al16((uint32_t)c * nb * kOT * 4u);
+  o += al16((uint32_t)(kOW * (cw + 1)) * 4u);
   L.sgn = o;
   o += kOW * 32 * 4;
   L.wsum = o;
@@ -79,6 +83,17 @@ __device__ __forceinline__ void own_load(const Pass1Args& a, int gc, int64_t tl,
                                          float (&v)[16]) {
   const float* p = gc < a.d ? reinterpret_cast<const float*>(a.A) + (int64_t)gc * a.lda
                             : reinterpret_cast<const float*>(a.b);
+  if (vok && tl + kORowsWave <= a.n) {  // the wave's whole span is inside X (wave-uniform)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 x = *reinterpret_cast<const float4*>(p + tl + 4 * lane + 256 * k);
+      v[4 * k + 0] = x.x;
+      v[4 * k + 1] = x.y;
+      v[4 * k + 2] = x.z;
+      v[4 * k + 3] = x.w;
+    }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int64_t j = tl + 4 * lane + 256 * k;
@@ -124,28 +139,103 @@ __device__ __forceinline__ void own_position(uint32_t wb, uint32_t wc, uint32_t 
 
 }  // namespace
 
-template <int NB>
+// Producer half of a column: take the prefetched column (and prefetch the
+// next one), apply D and the sign of the b column, store 4 C_k u of the
+// I-half copies into their slots of staging array `buf`, run the
+// butterflies, store 4 C_k (H u) / sqrt(s) of the H-half copies.
+template <int LOG2S>
+__device__ __forceinline__ void own_produce(const Pass1Args& a, unsigned char* sb, int col, int c0,
+                                           int cs, int64_t tl, int lane, int L, bool vok,
+                                           const uint32_t (&sm)[16], const float (&cI)[16],
+                                           const float (&cH)[16], const uint32_t (&slI)[16],
+                                           const uint32_t (&slH)[16], float (&vn)[16]) {
+  float v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = vn[r];
+  if (col + 1 < cs) own_load(a, c0 + col + 1, tl, lane, vok, vn);
+  const uint32_t negb = (a.b && c0 + col == a.d) ? 0x80000000u : 0u;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    v[r] = __uint_as_float(xor3(__float_as_uint(v[r]), sm[r], negb));
+    *reinterpret_cast<float*>(sb + slI[r]) = cI[r] * v[r];
+  }
+  fwht_span1024_t<LOG2S>(v, L);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) *reinterpret_cast<float*>(sb + slH[r]) = cH[r] * v[r];
+}
+
+// Owner half of a column: the sums of this lane's buckets' segments of
+// staging array `sb`, in slot order, added into the column's FP64
+// accumulators.
+template <int NB, int CMAX>
+__device__ __forceinline__ void own_sum(const unsigned char* sb, int col, int span,
+                                       const uint32_t (&seg0)[NB], const uint32_t (&seg1)[NB],
+                                       double (&m)[NB][CMAX]) {
+  const float2* st2 = reinterpret_cast<const float2*>(sb);
+  float sacc[NB];
+  if (span >= 256) {
+    // about 2 * 8192 / span <= 64 terms per segment: FP32 (two chains, even
+    // and odd slots) is within 64 u of the segment's l1 mass
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      float se = 0.0f, so = 0.0f;
+#pragma unroll 4
+      for (uint32_t q2 = seg0[u] >> 1; q2 < (seg1[u] >> 1); ++q2) {
+        const float2 x = st2[q2];
+        se += x.x;
+        so += x.y;
+      }
+      sacc[u] = se + so;
+    }
+  } else {
+    // long segments (few buckets): FP64
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      double se = 0.0, so = 0.0;
+#pragma unroll 4
+      for (uint32_t q2 = seg0[u] >> 1; q2 < (seg1[u] >> 1); ++q2) {
+        const float2 x = st2[q2];
+        se += (double)x.x;
+        so += (double)x.y;
+      }
+      sacc[u] = (float)(se + so);
+    }
+  }
+  // into the accumulators of column col: col is uniform, and the empty asm
+  // keeps each case a scalar branch rather than selects over every column
+#pragma unroll
+  for (int cc = 0; cc < CMAX; ++cc)
+    if (cc == col) {
+      asm volatile("");
+#pragma unroll
+      for (int u = 0; u < NB; ++u) m[u][cc] += (double)sacc[u];
+    }
+}
+
+template <int NB, int LOG2S>
 __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_ok) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int CMAX = NB == 2 ? kOColsNB2 : kOColsNB1;
+  constexpr uint32_t S = 1u << LOG2S;
   const int c0 = blockIdx.y * a.c;
   const int cs = min(a.c, a.q - c0);
   const int blo = blockIdx.z * a.bucket_span;
   const int span = min(a.bucket_span, a.r1 - blo);
-  const int cw = NB == 2 ? (span + 1) >> 1 : span;  // counter words per wave
-  const OwnLayout Ly = own_layout(a.bucket_span, a.c);
+  const int cw = NB == 2 ? (span + 1) >> 1 : span;  // counter words per wave (+1 spare below)
+  const OwnLayout Ly = own_layout(a.bucket_span);
   float* stage = reinterpret_cast<float*>(smem + Ly.stage);
   uint32_t* cnt = reinterpret_cast<uint32_t*>(smem + Ly.cnt);
-  float* tsum = reinterpret_cast<float*>(smem + Ly.tsum);
   uint32_t* sgn = reinterpret_cast<uint32_t*>(smem + Ly.sgn);
   uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + Ly.wsum);
-  const uint32_t trash = (uint32_t)(kOPos + span) * 4u;  // discard slot (bucket outside the range)
+  // a position whose bucket is outside the workgroup's range is counted in a
+  // spare counter word and stored into a discard slot
+  const uint32_t trash = 4u * (uint32_t)(kOPos + span);
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, L = lane & 15;
   const bool vok = vec_ok != 0;
-  const int log2s = a.log2s;
-  const float scale_h = a.scale_h;
-  uint32_t* mycnt = cnt + wave * cw;
+  // 4 / sqrt(s) and the sign the butterflies leave in this lane
+  const float scale_h = a.scale_h * span_sign(L, LOG2S);
+  uint32_t* mycnt = cnt + wave * (cw + 1);
 
   double m[NB][CMAX];
 #pragma unroll
@@ -157,24 +247,26 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
   const int64_t tiles_end = (a.n_pad + kOTile - 1) / kOTile * kOTile;
   const int64_t row1 = min(tiles_end, row0 + a.rows_per_range);
 
-  float v[16], vn[16], cI[16], cH[16];
+  float vn[16], cI[16], cH[16];
   uint32_t sm[16], slI[16], slH[16];
 
   for (int64_t tile = row0; tile < row1; tile += kOTile) {
     const int64_t tl = tile + (int64_t)wave * kORowsWave;  // window-local first row of this wave
-    const uint64_t jg0 = (uint64_t)a.row0g + (uint64_t)tl;  // its global row
+    const uint64_t jg0 = (uint64_t)a.row0g + (uint64_t)tl;  // its global row (a multiple of s)
     own_load(a, c0, tl, lane, vok, vn);                     // column 0, in flight during set-up
 
     // ---- set-up of the tile (independent of X) ----
-    for (int i = tid; i < kOW * cw; i += kOT) cnt[i] = 0u;
+    for (int i = tid; i < kOW * (cw + 1); i += kOT) cnt[i] = 0u;
     if (a.sign_flip && lane < 8) {
       const uint4 sw = stream_words(a.seed, kStreamSign, (jg0 >> 7) + (uint64_t)lane, a.instance);
       *reinterpret_cast<uint4*>(&sgn[wave * 32 + 4 * lane]) = sw;
     }
     // Bucket and Cauchy of the 32 positions, one pair of rows per step: the
     // I-half copies, then the H-half ones, each half through this thread's
-    // 16 slots of the staging array (unused until the columns start), so that
-    // only one step's values are live at a time.
+    // 16 slots of the staging area (unused until the columns start), so that
+    // only one step's values are live at a time.  Row jg0 + t of the wave's
+    // span has its H-half copy at 2 jg0 + 2 s (t >> log2 s) + (t mod s): jg0
+    // is a multiple of s, so the call index is jg0 plus a 32-bit offset.
     {
       uint2* scr = reinterpret_cast<uint2*>(stage);
       int lane_o = lane;
@@ -184,10 +276,10 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
 #pragma unroll 1
         for (int g = 0; g < 8; ++g) {
           const int k = g >> 1, p = g & 1, r = 4 * k + 2 * p;
-          const uint64_t j = jg0 + (uint64_t)(hh ? span_row_out(lane_o, r, log2s)
-                                                  : 2 * p + 4 * lane_o + 256 * k);
-          const uint64_t pos = h_position(j, log2s) + (hh ? 0ull : (1ull << log2s));
-          const uint4 w = stream_words(a.seed, kStreamPi1, pos >> 1, a.instance);
+          const uint32_t t = hh ? (uint32_t)span_row_out(lane_o, r, LOG2S)
+                                : (uint32_t)(2 * p + 4 * lane_o + 256 * k);
+          const uint32_t hloc = ((t >> LOG2S) << (LOG2S + 1)) + (t & (S - 1)) + (hh ? 0u : S);
+          const uint4 w = stream_words(a.seed, kStreamPi1, jg0 + (hloc >> 1), a.instance);
           const float sc = hh ? scale_h : 4.0f;
           uint32_t k0, k1;
           float c0v, c1v;
@@ -226,23 +318,18 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
     }
     __syncthreads();  // counters cleared
 
-    // ranks within (wave, bucket), from the counter adds
+    // ranks within (wave, bucket), from the counter adds; keys outside the
+    // bucket range count in the spare word cw
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         uint32_t& key = h ? slH[r] : slI[r];
-        if (key != 0xFFFFFFFFu) {
-          const uint32_t lb = key >> 16;
-          uint32_t rank;
-          if (NB == 2) {
-            const uint32_t sh = (lb & 1u) * 16u;
-            rank = (atomicAdd(&mycnt[lb >> 1], 1u << sh) >> sh) & 0xFFFFu;
-          } else {
-            rank = atomicAdd(&mycnt[lb], 1u);
-          }
-          key |= rank;
-        }
+        const uint32_t lb = key >> 16;  // 0xFFFF outside the range
+        const uint32_t word = NB == 2 ? min(lb >> 1, (uint32_t)cw) : min(lb, (uint32_t)cw);
+        const uint32_t sh = NB == 2 ? (lb & 1u) << 4 : 0u;
+        const uint32_t old = atomicAdd(&mycnt[word], 1u << sh);
+        key = (key & 0xFFFF0000u) | (NB == 2 ? __builtin_amdgcn_ubfe(old, sh, 16) : (old & 0xFFFFu));
       }
     __syncthreads();  // counts complete
 
@@ -255,7 +342,7 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
       if (tid < cw) {
 #pragma unroll
         for (int w = 0; w < kOW; ++w) {
-          const uint32_t cv = cnt[w * cw + tid];
+          const uint32_t cv = cnt[w * (cw + 1) + tid];
           if (NB == 2) {
             tot[0] += cv & 0xFFFFu;
             tot[NB - 1] += cv >> 16;
@@ -275,7 +362,10 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
       for (int u = 0; u < NB; ++u) {
         seg0[u] = base;
         seg1[u] = base + padded[u];
-        if (tot[u] & 1u) stage[base + tot[u]] = 0.0f;  // pad the segment with a zero
+        if (tot[u] & 1u) {  // pad the segment with a zero, in both staging arrays
+          stage[base + tot[u]] = 0.0f;
+          stage[Ly.stage_bytes / 4 + base + tot[u]] = 0.0f;
+        }
         base += padded[u];
       }
       if (tid < cw) {
@@ -284,98 +374,56 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
         for (int u = 0; u < NB; ++u) run[u] = seg0[u];
 #pragma unroll
         for (int w = 0; w < kOW; ++w) {
-          const uint32_t cv = cnt[w * cw + tid];
+          const uint32_t cv = cnt[w * (cw + 1) + tid];
           if (NB == 2) {
-            cnt[w * cw + tid] = run[0] | (run[NB - 1] << 16);
+            cnt[w * (cw + 1) + tid] = run[0] | (run[NB - 1] << 16);
             run[0] += cv & 0xFFFFu;
             run[NB - 1] += cv >> 16;
           } else {
-            cnt[w * cw + tid] = run[0];
+            cnt[w * (cw + 1) + tid] = run[0];
             run[0] += cv;
           }
         }
       }
     }
     __syncthreads();  // offsets complete
+    // slots as byte offsets within a staging array
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         uint32_t& key = h ? slH[r] : slI[r];
-        if (key != 0xFFFFFFFFu) {
-          const uint32_t lb = key >> 16;
-          uint32_t off;
-          if (NB == 2) off = (mycnt[lb >> 1] >> ((lb & 1u) * 16u)) & 0xFFFFu;
-          else off = mycnt[lb];
-          key = (off + (key & 0xFFFFu)) * 4u;
-        } else {
-          key = trash;
-        }
+        const uint32_t lb = key >> 16;
+        const uint32_t word = NB == 2 ? min(lb >> 1, (uint32_t)cw) : min(lb, (uint32_t)cw);
+        const uint32_t off = NB == 2 ? __builtin_amdgcn_ubfe(mycnt[word], (lb & 1u) << 4, 16)
+                                     : mycnt[word];
+        key = lb < (uint32_t)span ? 4u * (off + (key & 0xFFFFu)) : trash;
       }
 
-    // ---- the slice's columns ----
+    // ---- the slice's columns, alternating between the two staging arrays ----
+    // Column col goes through array col & 1.  After the barrier that
+    // completes column col, a wave sums column col and produces column
+    // col + 1 into the other array, which is free: every wave finished its
+    // sums of column col - 1 before that barrier.  Waves 0-3 sum first and
+    // waves 4-7 produce first, so the two waves sharing a SIMD overlap the
+    // LDS-bound sums with the VALU-bound butterflies.
+    own_produce<LOG2S>(a, smem + Ly.stage, 0, c0, cs, tl, lane, L, vok, sm, cI, cH, slI, slH, vn);
+    __syncthreads();
+    const bool sum_first = wave < 4;
     for (int col = 0; col < cs; ++col) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = vn[r];
-      if (col + 1 < cs) own_load(a, c0 + col + 1, tl, lane, vok, vn);
-      const uint32_t negb = (a.b && c0 + col == a.d) ? 0x80000000u : 0u;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        v[r] = __uint_as_float(__float_as_uint(v[r]) ^ sm[r] ^ negb);
-        *reinterpret_cast<float*>(smem + Ly.stage + slI[r]) = cI[r] * v[r];
-      }
-      fwht_span1024(v, L, log2s);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) *reinterpret_cast<float*>(smem + Ly.stage + slH[r]) = cH[r] * v[r];
-      __syncthreads();  // the column's staging array is complete
-      float sacc[NB];
-      const float2* st2 = reinterpret_cast<const float2*>(stage);
-      if (span >= 256) {
-        // about 2 * 8192 / span <= 64 terms per segment: FP32 is within 64 u
-        // of the segment's l1 mass
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-          float sv = 0.0f;
-#pragma unroll 4
-          for (uint32_t q2 = seg0[u] >> 1; q2 < (seg1[u] >> 1); ++q2) {
-            const float2 x = st2[q2];
-            sv += x.x;
-            sv += x.y;
-          }
-          sacc[u] = sv;
-        }
+      unsigned char* cur = smem + Ly.stage + (col & 1) * Ly.stage_bytes;
+      unsigned char* nxt = smem + Ly.stage + ((col + 1) & 1) * Ly.stage_bytes;
+      if (sum_first) {
+        own_sum<NB, CMAX>(cur, col, span, seg0, seg1, m);
+        if (col + 1 < cs)
+          own_produce<LOG2S>(a, nxt, col + 1, c0, cs, tl, lane, L, vok, sm, cI, cH, slI, slH, vn);
       } else {
-        // long segments (few buckets): sum in FP64
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-          double sv = 0.0;
-#pragma unroll 4
-          for (uint32_t q2 = seg0[u] >> 1; q2 < (seg1[u] >> 1); ++q2) {
-            const float2 x = st2[q2];
-            sv += (double)x.x;
-            sv += (double)x.y;
-          }
-          sacc[u] = (float)sv;
-        }
+        if (col + 1 < cs)
+          own_produce<LOG2S>(a, nxt, col + 1, c0, cs, tl, lane, L, vok, sm, cI, cH, slI, slH, vn);
+        own_sum<NB, CMAX>(cur, col, span, seg0, seg1, m);
       }
-      if (NB == 2)
-        reinterpret_cast<float2*>(tsum)[col * kOT + tid] = make_float2(sacc[0], sacc[NB - 1]);
-      else
-        tsum[col * kOT + tid] = sacc[0];
-      __syncthreads();  // the staging array is rewritten by the next column
+      __syncthreads();  // column col + 1 complete; column col's array free again
     }
-    // parked per-column sums into the FP64 accumulators (written by this thread)
-#pragma unroll
-    for (int cc = 0; cc < CMAX; ++cc)
-      if (cc < cs) {
-        if (NB == 2) {
-          const float2 x = reinterpret_cast<const float2*>(tsum)[cc * kOT + tid];
-          m[0][cc] += (double)x.x;
-          m[NB - 1][cc] += (double)x.y;
-        } else {
-          m[0][cc] += (double)tsum[cc * kOT + tid];
-        }
-      }
   }
 
   float* part = reinterpret_cast<float*>(a.partials);
@@ -391,29 +439,36 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
     }
 }
 
-int pass1_owner_max_cols(int span) {
-  const int nb = span > 512 ? 2 : 1;
-  const int cap = nb == 2 ? kOColsNB2 : kOColsNB1;
-  int c = cap;
-  while (c > 1 && own_layout(span, c).total > 160u * 1024u) --c;
-  return c;
-}
+int pass1_owner_max_cols(int span) { return span > 512 ? kOColsNB2 : kOColsNB1; }
 
-size_t pass1_owner_lds(int span, int c) { return own_layout(span, c).total; }
+size_t pass1_owner_lds(int span, int c) {
+  (void)c;
+  return own_layout(span).total;
+}
 
 int pass1_owner_tile_rows() { return kOTile; }
 
-hipError_t launch_pass1_owner(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st) {
-  const bool two = a.bucket_span > 512;
-  const void* fn = two ? (const void*)pass1_owner_kernel<2> : (const void*)pass1_owner_kernel<1>;
+template <int NB>
+static hipError_t launch_owner_nb(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st) {
+  const void* fns[10] = {
+      (const void*)pass1_owner_kernel<NB, 1>, (const void*)pass1_owner_kernel<NB, 2>,
+      (const void*)pass1_owner_kernel<NB, 3>, (const void*)pass1_owner_kernel<NB, 4>,
+      (const void*)pass1_owner_kernel<NB, 5>, (const void*)pass1_owner_kernel<NB, 6>,
+      (const void*)pass1_owner_kernel<NB, 7>, (const void*)pass1_owner_kernel<NB, 8>,
+      (const void*)pass1_owner_kernel<NB, 9>, (const void*)pass1_owner_kernel<NB, 10>};
+  if (a.log2s < 1 || a.log2s > 10) return hipErrorInvalidValue;
+  const void* fn = fns[a.log2s - 1];
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds);
   if (e != hipSuccess) return e;
-  const dim3 grid(p.nranges, p.nslices, p.nbranges);
-  if (two)
-    hipLaunchKernelGGL(pass1_owner_kernel<2>, grid, dim3(kOT), p.lds, st, a, vec_ok ? 1 : 0);
-  else
-    hipLaunchKernelGGL(pass1_owner_kernel<1>, grid, dim3(kOT), p.lds, st, a, vec_ok ? 1 : 0);
-  return hipGetLastError();
+  Pass1Args aa = a;
+  int vo = vec_ok ? 1 : 0;
+  void* args[] = {&aa, &vo};
+  return hipLaunchKernel(fn, dim3(p.nranges, p.nslices, p.nbranges), dim3(kOT), args, p.lds, st);
+}
+
+hipError_t launch_pass1_owner(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st) {
+  return a.bucket_span > 512 ? launch_owner_nb<2>(a, p, vec_ok, st)
+                             : launch_owner_nb<1>(a, p, vec_ok, st);
 }
 
 }  // namespace fctl1

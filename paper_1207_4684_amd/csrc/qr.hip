@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) form_m_kernel(const double* __restrict__ 
                                                      double* __restrict__ Md, float* __restrict__ Mf,
                                                      float* __restrict__ Mfb,
                                                      uint16_t* __restrict__ Mb,
-                                                     int* __restrict__ status) {
+                                                     int* __restrict__ status, int gaussian) {
   __shared__ double Rs[96 * 96];
   __shared__ double Ms[96 * 32];
   for (int e = threadIdx.x; e < q * q; e += blockDim.x) Rs[e] = R[e];
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) form_m_kernel(const double* __restrict__ 
     double v = 0.0;
     if (c < r2) {
       const uint4 w = stream_words(seed, kStreamPi2, (uint64_t)a * r2 + c, instance);
-      v = cauchy_from_word_f64(w.x);
+      v = gaussian ? gaussian_from_words_f64(w.x, w.y) : cauchy_from_word_f64(w.x);
     }
     Ms[e] = v;
   }
@@ -215,10 +215,10 @@ __global__ void __launch_bounds__(256) form_m_kernel(const double* __restrict__ 
 
 hipError_t launch_form_m(const double* R, int q, int r2, int ldm, uint64_t seed,
                          uint32_t instance, double* Md, float* Mf, float* Mfb, uint16_t* Mb,
-                         int* status, hipStream_t st) {
+                         int* status, hipStream_t st, bool gaussian) {
   if (q > 96 || ldm > 32) return hipErrorInvalidValue;
   hipLaunchKernelGGL(form_m_kernel, dim3(1), dim3(256), 0, st, R, q, r2, ldm, seed, instance, Md,
-                     Mf, Mfb, Mb, status);
+                     Mf, Mfb, Mb, status, gaussian ? 1 : 0);
   return hipGetLastError();
 }
 

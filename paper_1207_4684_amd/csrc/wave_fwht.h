@@ -117,6 +117,42 @@ __device__ __forceinline__ void fwht_span1024(float (&v)[16], int L, int log2s) 
   if (log2s > 7) swap32_stage(v);
 }
 
+// The same transform with log2 s fixed at compile time and the DPP stages in
+// one instruction each: w <- w + sg * w_partner (v_fmac with the partner's
+// value read through DPP), sg = +1 in the lower lane and -1 in the upper one.
+// The lower lane gets x + y; the upper one gets y - x = -(x - y), so after
+// the stages over lane bits 0..m-1 a lane holds its outputs times
+// (-1)^popcount(L & (2^m - 1)) (span_sign).  Both lanes of a pair carry the
+// same sign before the stage (they differ only in the stage's bit), the
+// register stages and the permlane swaps keep the sign of the row of 16 they
+// work in, so the factor is per lane and the caller folds it into its
+// scaling.
+template <int B>
+__device__ __forceinline__ void lane_stage_signed(float (&v)[16], float sg) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = fmaf(lane_xor<B>(v[r]), sg, v[r]);
+}
+
+template <int LOG2S>
+__device__ __forceinline__ void fwht_span1024_t(float (&v)[16], int L) {
+  if constexpr (LOG2S > 0) reg_stage(v, 0);
+  if constexpr (LOG2S > 1) reg_stage(v, 1);
+  if constexpr (LOG2S > 8) reg_stage(v, 2);
+  if constexpr (LOG2S > 9) reg_stage(v, 3);
+  if constexpr (LOG2S > 2) lane_stage_signed<0>(v, (L & 1) ? -1.0f : 1.0f);
+  if constexpr (LOG2S > 3) lane_stage_signed<1>(v, (L & 2) ? -1.0f : 1.0f);
+  if constexpr (LOG2S > 4) lane_stage_signed<2>(v, (L & 4) ? -1.0f : 1.0f);
+  if constexpr (LOG2S > 5) lane_stage_signed<3>(v, (L & 8) ? -1.0f : 1.0f);
+  if constexpr (LOG2S > 6) swap16_stage(v);
+  if constexpr (LOG2S > 7) swap32_stage(v);
+}
+
+// the per-lane sign fwht_span1024_t leaves on its outputs
+__device__ __forceinline__ float span_sign(int L, int log2s) {
+  const int m = log2s > 6 ? 4 : (log2s > 2 ? log2s - 2 : 0);
+  return (__builtin_popcount(L & ((1 << m) - 1)) & 1) ? -1.0f : 1.0f;
+}
+
 // Row within the 1024-row span of value (lane, register r) after
 // fwht_span1024 with the given log2s.
 __device__ __forceinline__ int span_row_out(int lane, int r, int log2s) {

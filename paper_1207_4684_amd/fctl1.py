@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfctl1.so")
 FCT_F32, FCT_F64, FCT_BF16 = 0, 1, 2
 FCT_FLAG_NO_SIGN_FLIP = 1
 FCT_FLAG_DETERMINISTIC = 2
+FCT_FLAG_GAUSSIAN_PI2 = 4
 FCT_OPT_PASS1_KERNEL, FCT_OPT_PASS1_WGS_PER_CU, FCT_OPT_PASS1_TILE_THREADS = 1, 2, 3
 FCT_OPT_PASS2_WGS, FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS = 4, 5, 6
 FCT_P1_AUTO, FCT_P1_WAVE, FCT_P1_OWNER, FCT_P1_TILE = 0, 1, 2, 3
@@ -65,6 +66,8 @@ def _load():
                                              I64, U32, P]),
         "l1_sample_probs": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64, I64,
                                            P, P, P]),
+        "l1_sample_probs_ex": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64,
+                                              I64, U32, P, P, P]),
         "l1_coreset": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64,
                                       ctypes.POINTER(fct_params), I64, P, P, P, P, PI64]),
         "l1_regress": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64, D,
@@ -93,7 +96,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream", "fct_sketch",
             "fct_sketch_window",
-            "l1_sample_probs", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
+            "l1_sample_probs", "l1_sample_probs_ex", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
             "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
             "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option")
 
@@ -200,15 +203,22 @@ def fct_sketch_window(ctx, A, b, s, r1, seed, row0, flags=0):
     return Y.t()
 
 
-def l1_sample_probs(ctx, A, b, R, r2, seed, s_out, want_p=True):
-    """lambda (n, FP32), p (n, FP32) and sum lambda (FP64 device scalar)."""
+def l1_sample_probs(ctx, A, b, R, r2, seed, s_out, want_p=True, flags=0):
+    """lambda (n, FP32), p (n, FP32) and sum lambda (FP64 device scalar).
+    flags = FCT_FLAG_GAUSSIAN_PI2 calls l1_sample_probs_ex (Gaussian Pi2)."""
     n, d, lda = _cm(A)
     Rbuf = R.t().contiguous()  # column-major q x q storage of the logical R
     lam = torch.empty(n, dtype=torch.float32, device=A.device)
     p = torch.empty(n, dtype=torch.float32, device=A.device) if want_p else None
     tot = torch.empty(1, dtype=torch.float64, device=A.device)
-    _check(_lib.l1_sample_probs(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf), r2,
-                                seed, int(s_out), _ptr(lam), _ptr(p), _ptr(tot)), "l1_sample_probs")
+    if flags:
+        _check(_lib.l1_sample_probs_ex(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
+                                       r2, seed, int(s_out), flags, _ptr(lam), _ptr(p), _ptr(tot)),
+               "l1_sample_probs_ex")
+    else:
+        _check(_lib.l1_sample_probs(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
+                                    r2, seed, int(s_out), _ptr(lam), _ptr(p), _ptr(tot)),
+               "l1_sample_probs")
     return lam, p, tot
 
 
