@@ -168,6 +168,27 @@ int l1_sample_probs_ex(fct_ctx *ctx, const void *A, const void *b, int64_t n, in
                        double *sum_lambda);
 
 /*
+ * l1_sample_probs_noalloc: l1_sample_probs_ex for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It calls no allocating routine: its
+ * scratch (M = R^-1 Pi2 in FP64, FP32 and BF16 forms and the per-workgroup
+ * sums of lambda) lives in a static device array of 80 KiB per GPU, held
+ * until the process ends.  lambda and sum_lambda must be non-NULL (device
+ * FP32 [n] and FP64 scalar); p may be NULL.  q <= 65 (q <= 96 for FCT_F64).
+ * FCT_ERR_CAPACITY if the pass-2 grid chosen for n (FCT_OPT_PASS2_WGS) needs
+ * more partial sums than the array holds; FCT_ERR_HIP if the array's address
+ * could not be found on this device.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two contexts, two host
+ * threads) race and must be ordered by the caller.  Nothing in the array has
+ * to start at zero (every word a call reads it has written first).  Other
+ * arguments and results as l1_sample_probs_ex.
+ */
+int l1_sample_probs_noalloc(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
+                            int64_t lda, fct_dtype dt, const double *R, int32_t r2, uint64_t seed,
+                            int64_t s_out, uint32_t flags, float *lambda, float *p,
+                            double *sum_lambda);
+
+/*
  * l1_coreset: steps 1-7.  Row i is kept iff its stream-3 word is below
  * floor(p_i 2^32) (p_i formed in FP64); kept rows are listed in ascending
  * order.

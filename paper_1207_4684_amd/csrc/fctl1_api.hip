@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -14,6 +15,20 @@
 #include "fct_kernels.h"
 
 using namespace fctl1;
+
+// Scratch of l1_sample_probs_noalloc: M = R^-1 Pi2 in its four forms and the
+// per-workgroup partial sums of lambda, in a static device array (one copy
+// per GPU, alive until the process ends).  Host code never uses the symbol's
+// name as an address: fct_create looks up each device's copy once with
+// hipGetSymbolAddress and the entry point passes that pointer.
+static constexpr size_t kNoAllocBytes = 80 * 1024;
+static __device__ __align__(256) unsigned char g_noalloc_scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
 
 struct fct_ctx {
   int device = 0;
@@ -47,6 +62,7 @@ struct fct_ctx {
   hipGraphExec_t bgraph = nullptr;
   std::vector<char> bsig;       // signature of the captured batch
   std::map<int, int> tuned_s;   // (d << 1 | f64) -> FWHT block size
+  void* noalloc = nullptr;      // this device's copy of g_noalloc_scratch (nullptr: lookup failed)
 };
 
 namespace {
@@ -455,6 +471,20 @@ int fct_create(fct_ctx** out, int device, void* hip_stream) {
     }
     c->own_stream = true;
   }
+  if (device >= 0 && device < kNoAllocMaxDevices) {
+    // once per device, with the device current: the address of its copy of
+    // the static scratch (a failed lookup leaves only the no-allocation entry
+    // point unusable)
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch)) == hipSuccess && ptr)
+        g_noalloc_ptr[device] = ptr;
+      else
+        (void)hipGetLastError();
+    }
+    c->noalloc = g_noalloc_ptr[device];
+  }
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
     c->cus = v;
@@ -639,6 +669,36 @@ int l1_sample_probs_ex(fct_ctx* c, const void* A, const void* b, int64_t n, int3
     SelectArgs a{};
     a.lambda = lam;
     a.sum_lambda = sl;
+    a.n = n;
+    a.s_out = (double)s_out;
+    a.p_out = p;
+    HIP_TRY(launch_probs_only(a, c->stream));
+  }
+  return FCT_OK;
+}
+
+int l1_sample_probs_noalloc(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d,
+                            int64_t lda, fct_dtype dt, const double* R, int32_t r2, uint64_t seed,
+                            int64_t s_out, uint32_t flags, float* lambda, float* p,
+                            double* sum_lambda) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (dt != FCT_F32 && dt != FCT_F64 && dt != FCT_BF16) return FCT_ERR_BAD_ARG;
+  if (!R || r2 < 1 || r2 > 32 || s_out < 1 || !lambda || !sum_lambda) return FCT_ERR_BAD_ARG;
+  const int q = d + (b ? 1 : 0);
+  if (q > (dt == FCT_F64 ? 96 : 65)) return FCT_ERR_BAD_ARG;
+  if (!c->noalloc) return FCT_ERR_HIP;
+  const int kind = dt == FCT_F64 ? kPass2F64 : (dt == FCT_BF16 ? kPass2BF16 : kPass2F32);
+  Measure m;
+  carve_probs(m, c, q, r2, n, kind);
+  if (m.off > kNoAllocBytes) return FCT_ERR_CAPACITY;  // a pass-2 grid above the scratch
+  Carve cv(reinterpret_cast<char*>(c->noalloc));
+  if ((st = run_probs(c, cv, A, b, n, d, lda, dt, R, r2, seed, lambda, sum_lambda, flags)))
+    return st;
+  if (p) {
+    SelectArgs a{};
+    a.lambda = lambda;
+    a.sum_lambda = sum_lambda;
     a.n = n;
     a.s_out = (double)s_out;
     a.p_out = p;

@@ -68,6 +68,8 @@ def _load():
                                            P, P, P]),
         "l1_sample_probs_ex": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64,
                                               I64, U32, P, P, P]),
+        "l1_sample_probs_noalloc": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32,
+                                                   U64, I64, U32, P, P, P]),
         "l1_coreset": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64,
                                       ctypes.POINTER(fct_params), I64, P, P, P, P, PI64]),
         "l1_regress": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, I64, D,
@@ -96,7 +98,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream", "fct_sketch",
             "fct_sketch_window",
-            "l1_sample_probs", "l1_sample_probs_ex", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
+            "l1_sample_probs", "l1_sample_probs_ex", "l1_sample_probs_noalloc", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
             "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
             "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option")
 
@@ -219,6 +221,17 @@ def l1_sample_probs(ctx, A, b, R, r2, seed, s_out, want_p=True, flags=0):
         _check(_lib.l1_sample_probs(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
                                     r2, seed, int(s_out), _ptr(lam), _ptr(p), _ptr(tot)),
                "l1_sample_probs")
+    return lam, p, tot
+
+
+def l1_sample_probs_noalloc(ctx, A, b, R, r2, seed, s_out, lam, tot, p=None, flags=0):
+    """l1_sample_probs_noalloc: lambda, p, sum lambda into caller-provided
+    device tensors (lam FP32 [n], tot FP64 [1], p FP32 [n] or None)."""
+    n, d, lda = _cm(A)
+    Rbuf = R.t().contiguous()
+    _check(_lib.l1_sample_probs_noalloc(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
+                                        r2, seed, int(s_out), flags, _ptr(lam), _ptr(p), _ptr(tot)),
+           "l1_sample_probs_noalloc")
     return lam, p, tot
 
 
