@@ -135,18 +135,42 @@ def _cm(A):
 
 
 class Context:
-    """fct_create / fct_destroy: binds a device and (by default) torch's current stream."""
+    """fct_create / fct_destroy on a device.
+
+    The library enqueues on its context's stream.  When torch's current stream
+    is the legacy default stream (handle 0) the library creates a stream of
+    its own, which is not ordered with torch's; every call through this
+    module is therefore bracketed: the library's stream first waits for
+    torch's current stream (inputs written by torch are complete), and torch's
+    current stream then waits for the library's (its outputs are complete
+    before torch reads them or reuses the memory of temporaries freed after
+    the call).  With a stream of the caller's choosing the two coincide and
+    the bracket is empty."""
 
     def __init__(self, device: int = 0, stream=None):
         dev = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(dev)
-        self.stream = stream
         self.device = device
         h = ctypes.c_void_p()
         _check(_lib.fct_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)),
                "fct_create")
         self.handle = h
+        self.lib_stream = _lib.fct_stream(h) or 0
+        self.stream = (stream if self.lib_stream == stream.cuda_stream
+                       else torch.cuda.ExternalStream(self.lib_stream, device=dev))
+
+    def call(self, fn, *args):
+        """fn(*args) with the library's stream ordered after torch's current
+        stream, and torch's current stream ordered after the library's."""
+        cur = torch.cuda.current_stream(self.device)
+        same = cur.cuda_stream == self.lib_stream
+        if not same:
+            self.stream.wait_stream(cur)
+        st = fn(*args)
+        if not same:
+            cur.wait_stream(self.stream)
+        return st
 
     def close(self):
         if self.handle:
@@ -160,7 +184,7 @@ class Context:
             pass
 
     def sync(self):
-        _check(_lib.fct_sync(self.handle), "fct_sync")
+        _check(self.call(_lib.fct_sync, self.handle), "fct_sync")
 
     def set_option(self, option: int, value: int):
         """fct_set_option: plan options (pass-1 kernel, grid sizes)."""
@@ -189,7 +213,7 @@ def fct_sketch(ctx, A, b, s, r1, seed, flags=0, want_y=True, want_r=True):
     q = d + (1 if b is not None else 0)
     Y = torch.empty((q, r1), dtype=A.dtype, device=A.device) if want_y else None
     R = torch.empty((q, q), dtype=torch.float64, device=A.device) if want_r else None
-    _check(_lib.fct_sketch(ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed, flags,
+    _check(ctx.call(_lib.fct_sketch, ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed, flags,
                            _ptr(Y), _ptr(R)), "fct_sketch")
     return (Y.t() if Y is not None else None), (R.t() if R is not None else None)
 
@@ -200,7 +224,7 @@ def fct_sketch_window(ctx, A, b, s, r1, seed, row0, flags=0):
     n, d, lda = _cm(A)
     q = d + (1 if b is not None else 0)
     Y = torch.empty((q, r1), dtype=A.dtype, device=A.device)
-    _check(_lib.fct_sketch_window(ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed,
+    _check(ctx.call(_lib.fct_sketch_window, ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed,
                                   int(row0), flags, _ptr(Y)), "fct_sketch_window")
     return Y.t()
 
@@ -214,11 +238,11 @@ def l1_sample_probs(ctx, A, b, R, r2, seed, s_out, want_p=True, flags=0):
     p = torch.empty(n, dtype=torch.float32, device=A.device) if want_p else None
     tot = torch.empty(1, dtype=torch.float64, device=A.device)
     if flags:
-        _check(_lib.l1_sample_probs_ex(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
+        _check(ctx.call(_lib.l1_sample_probs_ex, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
                                        r2, seed, int(s_out), flags, _ptr(lam), _ptr(p), _ptr(tot)),
                "l1_sample_probs_ex")
     else:
-        _check(_lib.l1_sample_probs(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
+        _check(ctx.call(_lib.l1_sample_probs, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
                                     r2, seed, int(s_out), _ptr(lam), _ptr(p), _ptr(tot)),
                "l1_sample_probs")
     return lam, p, tot
@@ -229,7 +253,7 @@ def l1_sample_probs_noalloc(ctx, A, b, R, r2, seed, s_out, lam, tot, p=None, fla
     device tensors (lam FP32 [n], tot FP64 [1], p FP32 [n] or None)."""
     n, d, lda = _cm(A)
     Rbuf = R.t().contiguous()
-    _check(_lib.l1_sample_probs_noalloc(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
+    _check(ctx.call(_lib.l1_sample_probs_noalloc, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(Rbuf),
                                         r2, seed, int(s_out), flags, _ptr(lam), _ptr(p), _ptr(tot)),
            "l1_sample_probs_noalloc")
     return lam, p, tot
@@ -244,7 +268,7 @@ def l1_coreset(ctx, A, b, prm, cap, A_lowp=None, b_lowp=None):
     idx = torch.empty(cap, dtype=torch.int64, device=A.device)
     S = ctypes.c_int64()
     ld_lowp = A_lowp.stride(0) if A_lowp is not None else 0
-    st = _lib.l1_coreset(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(A_lowp),
+    st = ctx.call(_lib.l1_coreset, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(A_lowp),
                          _ptr(b_lowp), ld_lowp, ctypes.byref(prm), cap, _ptr(At), _ptr(bt),
                          _ptr(w), _ptr(idx), ctypes.byref(S))
     _check(st, "l1_coreset")
@@ -260,7 +284,7 @@ def l1_regress(ctx, A, b, prm, eps=0.05, A_lowp=None, b_lowp=None):
     obj = ctypes.c_double()
     S = ctypes.c_int64()
     ld_lowp = A_lowp.stride(0) if A_lowp is not None else 0
-    st = _lib.l1_regress(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(A_lowp),
+    st = ctx.call(_lib.l1_regress, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), _ptr(A_lowp),
                          _ptr(b_lowp), ld_lowp, eps, ctypes.byref(prm), x, ctypes.byref(obj),
                          ctypes.byref(S))
     _check(st, "l1_regress")
@@ -273,7 +297,7 @@ def l1_select(ctx, lam, sum_lambda, s_out, seed, cap):
     idx = torch.empty(cap, dtype=torch.int64, device=lam.device)
     w = torch.empty(cap, dtype=torch.float64, device=lam.device)
     S = ctypes.c_int64()
-    _check(_lib.l1_select(ctx.handle, _ptr(lam), _ptr(sum_lambda), n, int(s_out), seed, cap,
+    _check(ctx.call(_lib.l1_select, ctx.handle, _ptr(lam), _ptr(sum_lambda), n, int(s_out), seed, cap,
                           _ptr(idx), _ptr(w), ctypes.byref(S)), "l1_select")
     return idx[:S.value], w[:S.value], S.value
 
@@ -304,7 +328,7 @@ def l1_regress_batched(ctx, items, eps=0.05):
     S = (ctypes.c_int64 * count)()
     s_used = (ctypes.c_int32 * count)()
     status = (ctypes.c_int32 * count)()
-    st = _lib.l1_regress_batched(ctx.handle, arr, count, dt, eps, x, obj, S, s_used, status)
+    st = ctx.call(_lib.l1_regress_batched, ctx.handle, arr, count, dt, eps, x, obj, S, s_used, status)
     if st not in (0, -4, -6, -5) or (st != 0 and all(v == 0 for v in status)):
         _check(st, "l1_regress_batched")
     out, off = [], 0
@@ -321,14 +345,14 @@ def l1_solve(ctx, At, bt, w, iters=0):
     S, d, ldat = _cm(At)
     x = (ctypes.c_double * d)()
     obj = ctypes.c_double()
-    _check(_lib.l1_solve(ctx.handle, _ptr(At), _ptr(bt), _ptr(w), S, d, ldat, _dt(At), iters, x,
+    _check(ctx.call(_lib.l1_solve, ctx.handle, _ptr(At), _ptr(bt), _ptr(w), S, d, ldat, _dt(At), iters, x,
                          ctypes.byref(obj)), "l1_solve")
     return np.array(x[:], dtype=np.float64), obj.value
 
 
 def fct_rng_words(ctx, stream, seed, idx0, count, device="cuda"):
     out = torch.empty(4 * count, dtype=torch.int32, device=device)
-    _check(_lib.fct_rng_words(ctx.handle, stream, seed, idx0, count, _ptr(out)), "fct_rng_words")
+    _check(ctx.call(_lib.fct_rng_words, ctx.handle, stream, seed, idx0, count, _ptr(out)), "fct_rng_words")
     return out
 
 
@@ -338,7 +362,7 @@ def fct_pi1_streams(ctx, seed, r1, s, j0, count, device="cuda"):
     bi = torch.empty(count, dtype=torch.int32, device=device)
     ci = torch.empty(count, dtype=torch.float32, device=device)
     sg = torch.empty(count, dtype=torch.int8, device=device)
-    _check(_lib.fct_pi1_streams(ctx.handle, seed, r1, s, j0, count, _ptr(bh), _ptr(ch), _ptr(bi),
+    _check(ctx.call(_lib.fct_pi1_streams, ctx.handle, seed, r1, s, j0, count, _ptr(bh), _ptr(ch), _ptr(bi),
                                 _ptr(ci), _ptr(sg)), "fct_pi1_streams")
     return bh, ch, bi, ci, sg
 
@@ -347,13 +371,13 @@ def fct_fwht(ctx, x, s):
     """In-place normalized FWHT of consecutive s-blocks of a float32 device vector."""
     if x.dtype != torch.float32 or x.numel() % s:
         raise ValueError("float32 tensor with a multiple of s elements expected")
-    _check(_lib.fct_fwht(ctx.handle, _ptr(x), x.numel() // s, s), "fct_fwht")
+    _check(ctx.call(_lib.fct_fwht, ctx.handle, _ptr(x), x.numel() // s, s), "fct_fwht")
     return x
 
 
 def fct_to_bf16(ctx, x):
     y = torch.empty(x.shape, dtype=torch.int16, device=x.device)
-    _check(_lib.fct_to_bf16(ctx.handle, _ptr(x.contiguous()), x.numel(), _ptr(y)), "fct_to_bf16")
+    _check(ctx.call(_lib.fct_to_bf16, ctx.handle, _ptr(x.contiguous()), x.numel(), _ptr(y)), "fct_to_bf16")
     return y
 
 
@@ -361,6 +385,6 @@ def fct_l1_objective(ctx, A, b, x):
     n, d, lda = _cm(A)
     xs = (ctypes.c_double * d)(*[float(v) for v in x])
     out = ctypes.c_double()
-    _check(_lib.fct_l1_objective(ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), xs,
+    _check(ctx.call(_lib.fct_l1_objective, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), xs,
                                  ctypes.byref(out)), "fct_l1_objective")
     return out.value

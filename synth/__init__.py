@@ -77,42 +77,55 @@ def _pick(n: int, count: int, seed: int, tag: int) -> np.ndarray:
     return np.sort(g.permutation(got)[:count])
 
 
+def chunk_context(w: Workload):
+    """What every chunk of workload w shares: x*, the column scales, and the
+    (sorted) high-leverage and outlier rows of the whole design."""
+    g0 = np.random.default_rng(np.random.SeedSequence([w.seed, 0]))
+    x_star = g0.standard_normal(w.d)
+    if w.col_scale_log10 > 0:
+        scale = 10.0 ** g0.uniform(-w.col_scale_log10, w.col_scale_log10, size=w.d)
+    else:
+        scale = np.ones(w.d)
+    lev = _pick(w.n, int(round(w.leverage_frac * w.n)), w.seed, 11)
+    out = _pick(w.n, int(round(w.outlier_frac * w.n)), w.seed, 12)
+    return x_star, scale, lev, out
+
+
+def generate_chunk(w: Workload, c: int, ctx=None):
+    """Rows [c 2^20, (c+1) 2^20) of workload w: (A (d, rows), b (rows,)),
+    the same bytes generate() puts there."""
+    x_star, scale, lev, out = ctx if ctx is not None else chunk_context(w)
+    lo, hi = c * CHUNK, min(w.n, (c + 1) * CHUNK)
+    dt = w.np_dtype
+    g = _rng(w.seed, 1, c)
+    blk = g.standard_normal((hi - lo, w.d)) * scale
+    sel = lev[(lev >= lo) & (lev < hi)] - lo
+    blk[sel] *= w.leverage_mult
+    Ac = blk.astype(dt)
+    if w.noise == "normal":
+        eps = g.normal(0.0, w.noise_scale, size=hi - lo)
+    else:
+        eps = g.laplace(0.0, w.noise_scale, size=hi - lo)
+    bc = Ac.astype(np.float64) @ x_star + eps
+    sel = out[(out >= lo) & (out < hi)] - lo
+    go = _rng(w.seed, 2, c)
+    bc[sel] = w.outlier_scale * go.standard_cauchy(sel.size)
+    return np.ascontiguousarray(Ac.T), bc.astype(dt)
+
+
 def generate(w: Workload, threads: int = 8):
     """Return (A (d, n) column-major, b (n,), x_star (d,)) for workload ``w``."""
-    n, d = w.n, w.d
-    dt = w.np_dtype
-    g0 = np.random.default_rng(np.random.SeedSequence([w.seed, 0]))
-    x_star = g0.standard_normal(d)
-    if w.col_scale_log10 > 0:
-        scale = 10.0 ** g0.uniform(-w.col_scale_log10, w.col_scale_log10, size=d)
-    else:
-        scale = np.ones(d)
-    A = np.empty((d, n), dtype=dt)
-    b = np.empty(n, dtype=dt)
-    lev = _pick(n, int(round(w.leverage_frac * n)), w.seed, 11)
-    out = _pick(n, int(round(w.outlier_frac * n)), w.seed, 12)
+    ctx = chunk_context(w)
+    A = np.empty((w.d, w.n), dtype=w.np_dtype)
+    b = np.empty(w.n, dtype=w.np_dtype)
 
     def work(chunk):
         c, lo, hi = chunk
-        g = _rng(w.seed, 1, c)
-        blk = g.standard_normal((hi - lo, d)) * scale
-        sel = lev[(lev >= lo) & (lev < hi)] - lo
-        blk[sel] *= w.leverage_mult
-        Ac = blk.astype(dt)
-        A[:, lo:hi] = Ac.T
-        if w.noise == "normal":
-            eps = g.normal(0.0, w.noise_scale, size=hi - lo)
-        else:
-            eps = g.laplace(0.0, w.noise_scale, size=hi - lo)
-        bc = Ac.astype(np.float64) @ x_star + eps
-        sel = out[(out >= lo) & (out < hi)] - lo
-        go = _rng(w.seed, 2, c)
-        bc[sel] = w.outlier_scale * go.standard_cauchy(sel.size)
-        b[lo:hi] = bc.astype(dt)
+        A[:, lo:hi], b[lo:hi] = generate_chunk(w, c, ctx)
 
     with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
-        list(ex.map(work, _chunks(n)))
-    return A, b, x_star
+        list(ex.map(work, _chunks(w.n)))
+    return A, b, ctx[0]
 
 
 def separable(n: int, d: int, seed: int = 0, outlier_frac: float = 0.001, dtype=np.float32):

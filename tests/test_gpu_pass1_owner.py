@@ -131,3 +131,30 @@ def test_owner_and_atomic_kernels_agree_to_tolerance(F, ctx):
     Yo_ = host(F.fct_sketch(ctx, dev(A), dev(b), 1024, 1024, 3, want_r=False)[0]).astype(np.float64)
     _, S = fct.pi1_apply(_x(A, b), 1024, 1024, 3, return_scale=True)
     assert np.all(np.max(np.abs(Yw - Yo_), axis=1) <= 2e-5 * S)
+
+
+def test_stream_ordering_without_synchronize(F):
+    """A context on torch's default stream: inputs made by torch kernels just
+    before the call, temporaries freed right after it and outputs read by torch
+    kernels, with no synchronize in between.  The owner sketch is bitwise
+    reproducible and doubling X doubles every sum exactly, so each round must
+    give exactly twice the reference."""
+    c = F.Context(0)
+    try:
+        n, d = 300000, 16
+        A = torch.randn(d, n, device="cuda")
+        b = torch.randn(n, device="cuda")
+        Y0 = F.fct_sketch(c, A, b, 1024, 1024, 13, want_r=False)[0]
+        torch.cuda.synchronize()
+        ref = (2.0 * Y0).clone()
+        for k in range(4):
+            A2, b2 = A * 2.0, b * 2.0          # torch kernels, not waited for
+            Y = F.fct_sketch(c, A2, b2, 1024, 1024, 13, want_r=False)[0]
+            del A2, b2                          # freed at once
+            junk = torch.full((d, n), float(k + 7), device="cuda")  # may reuse their memory
+            got = Y * 1.0                       # torch reads the library's output
+            del junk
+            torch.cuda.synchronize()
+            assert torch.equal(got.view(torch.int32), ref.view(torch.int32)), k
+    finally:
+        c.close()
