@@ -3,6 +3,7 @@
 // path (regression figure steps 1-8).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -190,7 +191,11 @@ Pass1Plan make_owner_plan(const fct_ctx* c, int64_t n_pad, int q, int r1) {
   int64_t nranges = (int64_t)c->cus * c->p1_waves_of_wgs / ((int64_t)p.nslices * p.nbranges);
   if (nranges < 1) nranges = 1;
   if (nranges > ntiles) nranges = ntiles;
-  const int64_t tpr = (ntiles + nranges - 1) / nranges;
+  int64_t tpr = (ntiles + nranges - 1) / nranges;
+  // the kernel's per-bucket accumulators are FP32: at most 16 tiles per
+  // range, unless that takes more than 4096 ranges (64 tiles at n = 2^31)
+  const int64_t tpr_cap = std::max<int64_t>(16, (ntiles + 4095) / 4096);
+  if (tpr > tpr_cap) tpr = tpr_cap;
   p.rows_per_range = tpr * tile;
   p.nranges = (int)((ntiles + tpr - 1) / tpr);
   return p;

@@ -174,16 +174,29 @@ __global__ void __launch_bounds__(1024) pass1_kernel(Pass1Args a) {
   }
 }
 
-// Y (r1 x q column-major) = sum over ranges of the partials, in range order, FP64.
+// Y (r1 x q column-major) = sum over ranges of the partials, FP64, in a
+// fixed order: a workgroup takes 64 consecutive entries, its wave g adds the
+// ranges g, g + 8, g + 16, ... in turn, and the eight wave sums are added in
+// wave order.
+constexpr int kRedGroups = 8;
+
 template <typename T>
-__global__ void reduce_partials_kernel(const T* __restrict__ part, int nranges, int r1, int q,
-                                       T* __restrict__ Y, double* __restrict__ Yd,
-                                       int* __restrict__ flag) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(64 * kRedGroups)
+reduce_partials_kernel(const T* __restrict__ part, int nranges, int r1, int q,
+                       T* __restrict__ Y, double* __restrict__ Yd, int* __restrict__ flag) {
+  __shared__ double ws[kRedGroups][64];
+  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + i;
   const int64_t tot = (int64_t)r1 * q;
-  if (idx >= tot) return;
   double s = 0.0;
-  for (int rr = 0; rr < nranges; ++rr) s += (double)part[(size_t)rr * tot + idx];
+  if (idx < tot)
+    for (int rr = g; rr < nranges; rr += kRedGroups) s += (double)part[(size_t)rr * tot + idx];
+  ws[g][i] = s;
+  __syncthreads();
+  if (g != 0 || idx >= tot) return;
+  s = ws[0][i];
+#pragma unroll
+  for (int k = 1; k < kRedGroups; ++k) s += ws[k][i];
   if (Yd) Yd[idx] = s;
   if (Y) Y[idx] = (T)s;
   if (!isfinite(s)) *flag = 1;
@@ -219,8 +232,8 @@ hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStr
 hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
                                   double* Yd, int* flag, bool f64, hipStream_t st) {
   const int64_t tot = (int64_t)r1 * q;
-  const int threads = 256;
-  const int blocks = (int)((tot + threads - 1) / threads);
+  const int threads = 64 * kRedGroups;
+  const int blocks = (int)((tot + 63) / 64);
   if (f64)
     hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(blocks), dim3(threads), 0, st,
                        (const double*)part, nranges, r1, q, (double*)Y, Yd, flag);

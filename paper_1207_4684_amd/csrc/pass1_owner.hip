@@ -23,16 +23,18 @@
 //      4 C_k (H u) / sqrt(s) of each H-half copy into its slot; after a barrier
 //      lane t sums its buckets' segments in slot order (FP32 when a bucket
 //      takes at most about 64 positions of a tile, FP64 otherwise) and adds
-//      the sums into its FP64 accumulators for that column (registers).
+//      the sums into its FP32 accumulators for that column (registers).
 //      Columns alternate between two staging arrays, so one barrier per
 //      column separates writers and readers, and half of the waves sum a
 //      column before producing the next one while the other half produce
 //      first, which overlaps sums and butterflies on every SIMD.
 // Nothing is added atomically to a sum: every sum is formed by one lane in an
 // order fixed by the random streams, so the sketch is the same bit for bit on
-// every run.  The FP64 accumulators are written once per workgroup as FP32
+// every run.  The accumulators are written once per workgroup as FP32
 // partials, which the reduction kernel adds in a fixed order.  Rows past the
 // padded end of X are loaded as zeros and add exact zeros.
+#include <type_traits>
+
 #include "fct_device.h"
 #include "fct_kernels.h"
 #include "wave_fwht.h"
@@ -139,20 +141,15 @@ __device__ __forceinline__ void own_position(uint32_t wb, uint32_t wc, uint32_t 
 
 }  // namespace
 
-// Producer half of a column: take the prefetched column (and prefetch the
-// next one), apply D and the sign of the b column, store 4 C_k u of the
-// I-half copies into their slots of staging array `buf`, run the
-// butterflies, store 4 C_k (H u) / sqrt(s) of the H-half copies.
+// Producer half of a column: take the column's loaded values v (consumed),
+// apply D and the sign of the b column, store 4 C_k u of the I-half copies
+// into their slots of staging array `sb`, run the butterflies, store
+// 4 C_k (H u) / sqrt(s) of the H-half copies.
 template <int LOG2S>
 __device__ __forceinline__ void own_produce(const Pass1Args& a, unsigned char* sb, int col, int c0,
-                                           int cs, int64_t tl, int lane, int L, bool vok,
-                                           const uint32_t (&sm)[16], const float (&cI)[16],
+                                           int L, const uint32_t (&sm)[16], const float (&cI)[16],
                                            const float (&cH)[16], const uint32_t (&slI)[16],
-                                           const uint32_t (&slH)[16], float (&vn)[16]) {
-  float v[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = vn[r];
-  if (col + 1 < cs) own_load(a, c0 + col + 1, tl, lane, vok, vn);
+                                           const uint32_t (&slH)[16], float (&v)[16]) {
   const uint32_t negb = (a.b && c0 + col == a.d) ? 0x80000000u : 0u;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -164,13 +161,40 @@ __device__ __forceinline__ void own_produce(const Pass1Args& a, unsigned char* s
   for (int r = 0; r < 16; ++r) *reinterpret_cast<float*>(sb + slH[r]) = cH[r] * v[r];
 }
 
+// Accumulators of one bucket for the columns of a slice, held in registers
+// and indexed by the (wave-uniform) column: a vector of 16 for columns 0-15
+// and one of HI for the rest.  A uniform index into such a vector is a
+// relative register move (s_set_gpr_idx), not a scratch access.  They are
+// FP32: a workgroup adds the sums of at most 64 tiles (16 unless the rows
+// would need more than 4096 ranges), so with segments of at most about 64
+// terms summed in two chains a bucket's sum is within about 100 u of its l1
+// mass; the ranges' partials are added in FP64.
+typedef float fvec16 __attribute__((ext_vector_type(16)));
+typedef float fvec8 __attribute__((ext_vector_type(8)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+
+template <int CMAX> struct ColAcc {
+  static_assert(CMAX == 18 || CMAX == 24, "slice widths of the owner kernel");
+  using Hi = typename std::conditional<CMAX == 18, fvec2, fvec8>::type;
+  fvec16 lo;
+  Hi hi;
+  __device__ __forceinline__ void zero() {
+    lo = 0.0f;
+    hi = 0.0f;
+  }
+  __device__ __forceinline__ void add(int col, float x) {
+    if (col < 16) lo[col] += x;
+    else hi[col - 16] += x;
+  }
+  __device__ __forceinline__ float get(int col) const { return col < 16 ? lo[col] : hi[col - 16]; }
+};
+
 // Owner half of a column: the sums of this lane's buckets' segments of
-// staging array `sb`, in slot order, added into the column's FP64
-// accumulators.
+// staging array `sb`, in slot order, added into the column's accumulators.
 template <int NB, int CMAX>
 __device__ __forceinline__ void own_sum(const unsigned char* sb, int col, int span,
                                        const uint32_t (&seg0)[NB], const uint32_t (&seg1)[NB],
-                                       double (&m)[NB][CMAX]) {
+                                       ColAcc<CMAX> (&m)[NB]) {
   const float2* st2 = reinterpret_cast<const float2*>(sb);
   float sacc[NB];
   if (span >= 256) {
@@ -201,15 +225,8 @@ __device__ __forceinline__ void own_sum(const unsigned char* sb, int col, int sp
       sacc[u] = (float)(se + so);
     }
   }
-  // into the accumulators of column col: col is uniform, and the empty asm
-  // keeps each case a scalar branch rather than selects over every column
 #pragma unroll
-  for (int cc = 0; cc < CMAX; ++cc)
-    if (cc == col) {
-      asm volatile("");
-#pragma unroll
-      for (int u = 0; u < NB; ++u) m[u][cc] += (double)sacc[u];
-    }
+  for (int u = 0; u < NB; ++u) m[u].add(col, sacc[u]);
 }
 
 template <int NB, int LOG2S>
@@ -237,23 +254,21 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
   const float scale_h = a.scale_h * span_sign(L, LOG2S);
   uint32_t* mycnt = cnt + wave * (cw + 1);
 
-  double m[NB][CMAX];
+  ColAcc<CMAX> m[NB];
 #pragma unroll
-  for (int u = 0; u < NB; ++u)
-#pragma unroll
-    for (int cc = 0; cc < CMAX; ++cc) m[u][cc] = 0.0;
+  for (int u = 0; u < NB; ++u) m[u].zero();
 
   const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_range;
   const int64_t tiles_end = (a.n_pad + kOTile - 1) / kOTile * kOTile;
   const int64_t row1 = min(tiles_end, row0 + a.rows_per_range);
 
-  float vn[16], cI[16], cH[16];
+  float v[16], cI[16], cH[16];
   uint32_t sm[16], slI[16], slH[16];
 
   for (int64_t tile = row0; tile < row1; tile += kOTile) {
     const int64_t tl = tile + (int64_t)wave * kORowsWave;  // window-local first row of this wave
     const uint64_t jg0 = (uint64_t)a.row0g + (uint64_t)tl;  // its global row (a multiple of s)
-    own_load(a, c0, tl, lane, vok, vn);                     // column 0, in flight during set-up
+    own_load(a, c0, tl, lane, vok, v);                      // column 0, in flight during set-up
 
     // ---- set-up of the tile (independent of X) ----
     for (int i = tid; i < kOW * (cw + 1); i += kOT) cnt[i] = 0u;
@@ -406,8 +421,11 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
     // col + 1 into the other array, which is free: every wave finished its
     // sums of column col - 1 before that barrier.  Waves 0-3 sum first and
     // waves 4-7 produce first, so the two waves sharing a SIMD overlap the
-    // LDS-bound sums with the VALU-bound butterflies.
-    own_produce<LOG2S>(a, smem + Ly.stage, 0, c0, cs, tl, lane, L, vok, sm, cI, cH, slI, slH, vn);
+    // LDS-bound sums with the VALU-bound butterflies.  The load of the next
+    // column to produce goes into v as soon as v is consumed and is in flight
+    // during a sum.
+    own_produce<LOG2S>(a, smem + Ly.stage, 0, c0, L, sm, cI, cH, slI, slH, v);
+    if (1 < cs) own_load(a, c0 + 1, tl, lane, vok, v);
     __syncthreads();
     const bool sum_first = wave < 4;
     for (int col = 0; col < cs; ++col) {
@@ -415,11 +433,15 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
       unsigned char* nxt = smem + Ly.stage + ((col + 1) & 1) * Ly.stage_bytes;
       if (sum_first) {
         own_sum<NB, CMAX>(cur, col, span, seg0, seg1, m);
-        if (col + 1 < cs)
-          own_produce<LOG2S>(a, nxt, col + 1, c0, cs, tl, lane, L, vok, sm, cI, cH, slI, slH, vn);
+        if (col + 1 < cs) {
+          own_produce<LOG2S>(a, nxt, col + 1, c0, L, sm, cI, cH, slI, slH, v);
+          if (col + 2 < cs) own_load(a, c0 + col + 2, tl, lane, vok, v);
+        }
       } else {
-        if (col + 1 < cs)
-          own_produce<LOG2S>(a, nxt, col + 1, c0, cs, tl, lane, L, vok, sm, cI, cH, slI, slH, vn);
+        if (col + 1 < cs) {
+          own_produce<LOG2S>(a, nxt, col + 1, c0, L, sm, cI, cH, slI, slH, v);
+          if (col + 2 < cs) own_load(a, c0 + col + 2, tl, lane, vok, v);
+        }
         own_sum<NB, CMAX>(cur, col, span, seg0, seg1, m);
       }
       __syncthreads();  // column col + 1 complete; column col's array free again
@@ -434,7 +456,7 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int bkt = NB * tid + u;
-        if (bkt < span) dst[bkt] = (float)m[u][cc];
+        if (bkt < span) dst[bkt] = m[u].get(cc);
       }
     }
 }

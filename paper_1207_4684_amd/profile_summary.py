@@ -4,6 +4,7 @@
     python -m paper_1207_4684_amd.profile_summary traffic FETCH_DB WRITE_DB \
         --kernel SUBSTR --copy-bytes N --algorithmic-bytes B
     python -m paper_1207_4684_amd.profile_summary pmc FETCH_DB WRITE_DB
+    python -m paper_1207_4684_amd.profile_summary counters DB [DB ...] --match SUBSTR
 
 ``stats`` prints calls, total, average, minimum and maximum device time per
 kernel from the kernel trace.  ``traffic`` reads one database collected with
@@ -13,6 +14,11 @@ copy kernel (``--copy-kernel``, a copy of ``--copy-bytes`` bytes reads and
 writes that many bytes) in the same run, and prints the HBM bytes per launch of the kernels
 whose names contain the ``--kernel`` substrings (summed), with the SHA-256 of the sources that build
 it so a reader can tell whether the figures still describe the current code.
+``counters`` prints the mean per dispatch of every counter in the databases
+for the kernels whose names contain ``--match``, and the ratios read from the
+shader-sequencer counters when they are present: VALU instructions per wave,
+the share of wave time a VALU instruction is issued, LDS bank-conflict cycles
+per LDS-busy cycle, and MFMA busy cycles per SQ busy cycle.
 """
 from __future__ import annotations
 
@@ -23,7 +29,8 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-PASS1_SOURCES = ("csrc/pass1_wave.hip", "csrc/fct_device.h")
+PASS1_SOURCES = ("csrc/pass1_owner.hip", "csrc/pass1_wave.hip", "csrc/wave_fwht.h",
+                 "csrc/fct_device.h")
 
 
 def source_sha256(files=PASS1_SOURCES) -> str:
@@ -131,6 +138,44 @@ def cmd_pmc(args):
         print(f"{_short(k, 80):80s} {n:10d} {f:12.1f} {w:12.1f} {mb:10.2f}")
 
 
+def all_counters(db: str, match: str):
+    """{kernel: {counter: mean per dispatch}} for kernels containing `match`."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select kernel_name, counter_name, dispatch_id, sum(value) from counters_collection "
+        "group by kernel_name, counter_name, dispatch_id").fetchall()
+    con.close()
+    agg: dict[str, dict[str, list[float]]] = {}
+    for k, c, _, v in rows:
+        if match in k:
+            agg.setdefault(k, {}).setdefault(c, []).append(float(v))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in agg.items()}
+
+
+def cmd_counters(args):
+    merged: dict[str, dict[str, float]] = {}
+    for db in args.dbs:
+        for k, cs in all_counters(db, args.match).items():
+            merged.setdefault(k, {}).update(cs)
+    for k in sorted(merged):
+        cs = merged[k]
+        print(f"kernel: {k}")
+        for c in sorted(cs):
+            print(f"  {c}: {cs[c]:.6g}")
+        waves = cs.get("SQ_WAVES")
+        if waves and "SQ_INSTS_VALU" in cs:
+            print(f"  valu_insts_per_wave: {cs['SQ_INSTS_VALU'] / waves:.1f}")
+        if cs.get("SQ_WAVE_CYCLES") and "SQ_ACTIVE_INST_VALU" in cs:
+            # both count in the same (quad-cycle) unit per wave
+            print(f"  valu_issue_share_of_wave_time: {cs['SQ_ACTIVE_INST_VALU'] / cs['SQ_WAVE_CYCLES']:.3f}")
+        if cs.get("SQ_ACTIVE_INST_LDS") and "SQ_LDS_BANK_CONFLICT" in cs:
+            print(f"  lds_bank_conflict_per_lds_active: "
+                  f"{cs['SQ_LDS_BANK_CONFLICT'] / cs['SQ_ACTIVE_INST_LDS']:.3f}")
+        if cs.get("SQ_BUSY_CYCLES") and "SQ_VALU_MFMA_BUSY_CYCLES" in cs:
+            print(f"  mfma_busy_per_sq_busy: "
+                  f"{cs['SQ_VALU_MFMA_BUSY_CYCLES'] / cs['SQ_BUSY_CYCLES']:.3f}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -149,8 +194,12 @@ def main(argv=None):
     m = sub.add_parser("pmc")
     m.add_argument("fetch_db")
     m.add_argument("write_db")
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--match", required=True)
     args = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "pmc": cmd_pmc}[args.cmd](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "pmc": cmd_pmc,
+     "counters": cmd_counters}[args.cmd](args)
 
 
 if __name__ == "__main__":
