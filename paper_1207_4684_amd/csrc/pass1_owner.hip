@@ -156,7 +156,7 @@ __device__ __forceinline__ void own_produce(const Pass1Args& a, unsigned char* s
     v[r] = __uint_as_float(xor3(__float_as_uint(v[r]), sm[r], negb));
     *reinterpret_cast<float*>(sb + slI[r]) = cI[r] * v[r];
   }
-  fwht_span1024_t<LOG2S>(v, L);
+  fwht_span1024_dpp<LOG2S>(v, L);
 #pragma unroll
   for (int r = 0; r < 16; ++r) *reinterpret_cast<float*>(sb + slH[r]) = cH[r] * v[r];
 }
@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(kOT) pass1_owner_kernel(Pass1Args a, int vec_o
 #pragma unroll 1
         for (int g = 0; g < 8; ++g) {
           const int k = g >> 1, p = g & 1, r = 4 * k + 2 * p;
-          const uint32_t t = hh ? (uint32_t)span_row_out(lane_o, r, LOG2S)
+          const uint32_t t = hh ? (uint32_t)span_row_out_dpp(lane_o, r, LOG2S)
                                 : (uint32_t)(2 * p + 4 * lane_o + 256 * k);
           const uint32_t hloc = ((t >> LOG2S) << (LOG2S + 1)) + (t & (S - 1)) + (hh ? 0u : S);
           const uint4 w = stream_words(a.seed, kStreamPi1, jg0 + (hloc >> 1), a.instance);

@@ -147,6 +147,68 @@ __device__ __forceinline__ void fwht_span1024_t(float (&v)[16], int L) {
   if constexpr (LOG2S > 7) swap32_stage(v);
 }
 
+// Signed DPP butterflies in one v_fmac_f32_dpp per value: v <- dpp(v) sg + v,
+// dpp(v) the partner lane's value under the stage's DPP control.  The
+// compiler does not see the DPP inside the asm, so the block keeps its own
+// wait states: a DPP read needs two after a VALU write of the register and
+// five after a scalar write of EXEC, hence the s_nop 4 in front; the
+// instructions of a block read and write distinct registers, and the
+// closing s_nop 1 covers whatever reads the results next.
+#define FCT_FMAC_DPP(i, ctrl) "v_fmac_f32_dpp %" #i ", %" #i ", %16 " ctrl " row_mask:0xf bank_mask:0xf\n\t"
+#define FCT_FMAC_DPP_BLOCK(ctrl)                                                                  \
+  asm("s_nop 4\n\t" FCT_FMAC_DPP(0, ctrl) FCT_FMAC_DPP(1, ctrl) FCT_FMAC_DPP(2, ctrl)           \
+          FCT_FMAC_DPP(3, ctrl) FCT_FMAC_DPP(4, ctrl) FCT_FMAC_DPP(5, ctrl) FCT_FMAC_DPP(6, ctrl) \
+              FCT_FMAC_DPP(7, ctrl) FCT_FMAC_DPP(8, ctrl) FCT_FMAC_DPP(9, ctrl)                   \
+                  FCT_FMAC_DPP(10, ctrl) FCT_FMAC_DPP(11, ctrl) FCT_FMAC_DPP(12, ctrl)            \
+                      FCT_FMAC_DPP(13, ctrl) FCT_FMAC_DPP(14, ctrl) FCT_FMAC_DPP(15, ctrl)        \
+      "s_nop 1"                                                                                   \
+      : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),    \
+        "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), \
+        "+v"(v[14]), "+v"(v[15])                                                                \
+      : "v"(sg))
+
+// partner lanes L ^ 1, L ^ 2 (quad_perm), L ^ 7 (row_half_mirror), L ^ 8 (row_ror:8)
+template <int P>
+__device__ __forceinline__ void lane_stage_fmac(float (&v)[16], float sg) {
+  if constexpr (P == 1) FCT_FMAC_DPP_BLOCK("quad_perm:[1,0,3,2]");
+  else if constexpr (P == 2) FCT_FMAC_DPP_BLOCK("quad_perm:[2,3,0,1]");
+  else if constexpr (P == 7) FCT_FMAC_DPP_BLOCK("row_half_mirror");
+  else {
+    static_assert(P == 8, "partner offsets of the DPP stages");
+    FCT_FMAC_DPP_BLOCK("row_ror:8");
+  }
+}
+
+// The transform of fwht_span1024_t with every lane stage one DPP instruction
+// per value.  Lane bit 2 has no single-instruction partner L ^ 4, so for
+// s >= 32 the stages over lane bits 0-2 run along L ^ 1, L ^ 2 and L ^ 7 in
+// the coordinates c0 = l0 ^ l2, c1 = l1 ^ l2, c2 = l2 of L (l_i its bits):
+// those partners differ in exactly one coordinate, so the three stages are
+// the size-8 transform over (c0, c1, c2), each stage's sign taken from its
+// own coordinate.  In lane coordinates the output of lane L is then the one
+// of index pi(L & 7) | (L & 8) (pi: see span_row_out_dpp)
+// with the sign span_sign(L, log2s), the same per-lane sign as in the
+// standard order.
+template <int LOG2S>
+__device__ __forceinline__ void fwht_span1024_dpp(float (&v)[16], int L) {
+  if constexpr (LOG2S > 0) reg_stage(v, 0);
+  if constexpr (LOG2S > 1) reg_stage(v, 1);
+  if constexpr (LOG2S > 8) reg_stage(v, 2);
+  if constexpr (LOG2S > 9) reg_stage(v, 3);
+  const int l0 = L & 1, l1 = (L >> 1) & 1, l2 = (L >> 2) & 1;
+  if constexpr (LOG2S > 4) {
+    lane_stage_fmac<1>(v, (l0 ^ l2) ? -1.0f : 1.0f);
+    lane_stage_fmac<2>(v, (l1 ^ l2) ? -1.0f : 1.0f);
+    lane_stage_fmac<7>(v, l2 ? -1.0f : 1.0f);
+  } else {
+    if constexpr (LOG2S > 2) lane_stage_fmac<1>(v, l0 ? -1.0f : 1.0f);
+    if constexpr (LOG2S > 3) lane_stage_fmac<2>(v, l1 ? -1.0f : 1.0f);
+  }
+  if constexpr (LOG2S > 5) lane_stage_fmac<8>(v, (L & 8) ? -1.0f : 1.0f);
+  if constexpr (LOG2S > 6) swap16_stage(v);
+  if constexpr (LOG2S > 7) swap32_stage(v);
+}
+
 // the per-lane sign fwht_span1024_t leaves on its outputs
 __device__ __forceinline__ float span_sign(int L, int log2s) {
   const int m = log2s > 6 ? 4 : (log2s > 2 ? log2s - 2 : 0);
@@ -162,6 +224,18 @@ __device__ __forceinline__ int span_row_out(int lane, int r, int log2s) {
   const int b6 = s6 ? k0 : l4, b8 = s6 ? l4 : k0;
   const int b7 = s7 ? k1 : l5, b9 = s7 ? l5 : k1;
   return i + 4 * (lane & 15) + 64 * b6 + 128 * b7 + 256 * b8 + 512 * b9;
+}
+
+// Row within the 1024-row span of value (lane, register r) after
+// fwht_span1024_dpp<log2s>: span_row_out of the lane whose low three bits
+// are pi(lane & 7), pi(k) = (k0 ^ k2) | (k1 ^ k2) << 1 | (k0 ^ k1 ^ k2) << 2,
+// when log2s >= 5.
+__device__ __forceinline__ int span_row_out_dpp(int lane, int r, int log2s) {
+  if (log2s > 4) {
+    const int k0 = lane & 1, k1 = (lane >> 1) & 1, k2 = (lane >> 2) & 1;
+    lane = (lane & ~7) | (k0 ^ k2) | ((k1 ^ k2) << 1) | ((k0 ^ k1 ^ k2) << 2);
+  }
+  return span_row_out(lane, r, log2s);
 }
 
 }  // namespace fctl1
