@@ -128,8 +128,8 @@ struct SelectArgs {
   uint64_t seed;
   uint32_t instance;
   float* p_out;        // optional
-  int32_t* counts;     // [grid]
-  int64_t* offsets;    // [grid + 1]
+  uint64_t* lookback;  // [grid + 1]: look-back status of each tile, then the ticket counter
+  int32_t* fail;       // device flag: FCT_ERR_HIP if the look-back wait timed out
   int64_t* idx;        // [cap]
   double* w;           // [cap]
   int64_t cap;

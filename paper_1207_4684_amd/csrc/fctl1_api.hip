@@ -436,8 +436,8 @@ int run_select(fct_ctx* c, Carve& cv, const float* lambda, const double* sum_lam
   a.seed = seed;
   a.instance = 0;
   a.p_out = nullptr;
-  a.counts = cv.take<int32_t>((size_t)nb);
-  a.offsets = cv.take<int64_t>((size_t)nb + 1);
+  a.lookback = cv.take<uint64_t>((size_t)nb + 1);
+  a.fail = c->flags + 1;
   a.idx = idx;
   a.w = w;
   a.cap = cap;
@@ -449,8 +449,7 @@ int run_select(fct_ctx* c, Carve& cv, const float* lambda, const double* sum_lam
 template <typename C>
 void carve_select(C& cv, int64_t n) {
   const int nb = select_grid(n);
-  cv.template take<int32_t>((size_t)nb);
-  cv.template take<int64_t>((size_t)nb + 1);
+  cv.template take<uint64_t>((size_t)nb + 1);
 }
 
 }  // namespace

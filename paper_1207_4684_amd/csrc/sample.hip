@@ -4,9 +4,14 @@
 //
 // Row i is kept iff its stream-3 word w_i satisfies w_i < floor(p_i 2^32),
 // with p_i formed in FP64 (the event "uniform < p_i" on the 2^-32 grid).
-// Kept rows are listed in ascending order: a first kernel counts the kept
-// rows of each 4096-row tile, one workgroup scans the counts, and a second
-// pass writes each tile's rows at its offset after an in-tile prefix sum.
+// Kept rows are listed in ascending order by one pass over lambda: a
+// workgroup takes the next 4096-row tile from a ticket counter, decides its
+// rows, publishes its count, and finds the count of all earlier tiles by
+// looking back over their published counts and prefixes (a decoupled
+// look-back scan); then it writes its rows at that offset after an in-tile
+// prefix sum.  Tiles are handed out in ticket order, so every tile a
+// workgroup waits for belongs to a workgroup that is already running.
+#include "../../include/fctl1.h"
 #include "fct_device.h"
 #include "fct_kernels.h"
 
@@ -26,9 +31,25 @@ __device__ __forceinline__ uint64_t threshold(float lam, double s_out, double to
   return (uint64_t)(t < 4294967296.0 ? t : 4294967296.0);
 }
 
-// keep mask of this thread's 16 consecutive rows (bit k = row base + k)
+// keep mask of this thread's 16 consecutive rows (bit k = row base + k);
+// base is a multiple of 16, so a whole group is four 16-byte loads
 __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base, double total,
                                               bool write_p) {
+  float lam[kSelRowsPerThread];
+  if (base + kSelRowsPerThread <= a.n) {
+    const float4* l4 = reinterpret_cast<const float4*>(a.lambda + base);
+#pragma unroll
+    for (int k = 0; k < kSelRowsPerThread / 4; ++k) {
+      const float4 x = l4[k];
+      lam[4 * k + 0] = x.x;
+      lam[4 * k + 1] = x.y;
+      lam[4 * k + 2] = x.z;
+      lam[4 * k + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSelRowsPerThread; ++k) lam[k] = base + k < a.n ? a.lambda[base + k] : 0.0f;
+  }
   uint32_t mask = 0;
 #pragma unroll
   for (int qd = 0; qd < kSelRowsPerThread / 4; ++qd) {
@@ -41,7 +62,7 @@ __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base,
       const int64_t i = r0 + k;
       if (i < a.n) {
         double p;
-        const uint64_t t = threshold(a.lambda[i], a.s_out, total, &p);
+        const uint64_t t = threshold(lam[4 * qd + k], a.s_out, total, &p);
         if (write_p && a.p_out) a.p_out[i] = (float)p;
         if ((uint64_t)ws[k] < t) mask |= 1u << (4 * qd + k);
       }
@@ -75,54 +96,91 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) 
   return sh[wave] + x - v;
 }
 
-__global__ void __launch_bounds__(kSelThreads) select_count_kernel(SelectArgs a) {
-  __shared__ int sh[kSelThreads / 64 + 1];
-  const double total = *a.sum_lambda;
-  const int64_t base = (int64_t)blockIdx.x * kSelRows + (int64_t)threadIdx.x * kSelRowsPerThread;
-  const uint32_t m = keep_mask(a, base, total, true);
-  int tot;
-  block_exclusive_scan(__popc(m), sh, &tot);
-  if (threadIdx.x == 0) a.counts[blockIdx.x] = tot;
+// Look-back status of a tile: the count of kept rows in the low 62 bits,
+// flag kAgg once the tile's own count is published, kPre once the count of
+// all tiles up to and including it is.
+constexpr uint64_t kAgg = 1ull << 62, kPre = 2ull << 62, kCountMask = (1ull << 62) - 1;
+// a wait longer than about a second means a tile will never be published:
+// the pass stops and reports FCT_ERR_HIP instead of waiting for ever
+constexpr uint32_t kLookbackSpins = 1u << 22;
+
+// The status word carries everything a reader needs (flag and count in one
+// 64-bit atomic), so the accesses are relaxed: agent-scope atomics that go
+// to the coherent cache level, without the whole-cache write-back and
+// invalidation that release and acquire ordering would add on every access.
+__device__ __forceinline__ uint64_t load_status(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_status(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(1024) scan_counts_kernel(const int32_t* __restrict__ counts,
-                                                           int nb, int64_t* __restrict__ offsets,
-                                                           int64_t* __restrict__ S) {
-  // one workgroup: each thread sums a contiguous run, then a scan of run totals
-  __shared__ int64_t run[1024];
-  const int T = blockDim.x;
-  const int per = (nb + T - 1) / T;
-  const int lo = threadIdx.x * per, hi = min(nb, lo + per);
-  int64_t s = 0;
-  for (int i = lo; i < hi; ++i) s += counts[i];
-  run[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t acc = 0;
-    for (int t = 0; t < T; ++t) {
-      const int64_t v = run[t];
-      run[t] = acc;
-      acc += v;
-    }
-    offsets[nb] = acc;
-    *S = acc;
-  }
-  __syncthreads();
-  int64_t o = run[threadIdx.x];
-  for (int i = lo; i < hi; ++i) {
-    offsets[i] = o;
-    o += counts[i];
-  }
+// status [nb] and the ticket counter status[nb] start at zero
+__global__ void select_init_kernel(uint64_t* __restrict__ status, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= nb) status[i] = 0ull;
 }
 
-__global__ void __launch_bounds__(kSelThreads) select_write_kernel(SelectArgs a) {
+__global__ void __launch_bounds__(kSelThreads) select_kernel(SelectArgs a, int nb) {
   __shared__ int sh[kSelThreads / 64 + 1];
+  __shared__ int s_tile;
+  __shared__ int64_t s_before;
+  uint64_t* status = a.lookback;
+  if (threadIdx.x == 0)
+    s_tile = (int)__hip_atomic_fetch_add(&status[nb], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int tile = s_tile;
   const double total = *a.sum_lambda;
-  const int64_t base = (int64_t)blockIdx.x * kSelRows + (int64_t)threadIdx.x * kSelRowsPerThread;
-  uint32_t m = keep_mask(a, base, total, false);
+  const int64_t base = (int64_t)tile * kSelRows + (int64_t)threadIdx.x * kSelRowsPerThread;
+  uint32_t m = keep_mask(a, base, total, a.p_out != nullptr);
   int tot;
   const int pre = block_exclusive_scan(__popc(m), sh, &tot);
-  int64_t pos = a.offsets[blockIdx.x] + pre;
+
+  if (threadIdx.x < 64) {
+    // wave 0: publish, then add the counts of the tiles before this one,
+    // 64 at a time (lane l looks at tile j - l), up to the nearest prefix
+    const int lane = threadIdx.x;
+    int64_t before = 0;
+    if (tile == 0) {
+      if (lane == 0) store_status(&status[0], kPre | (uint64_t)tot);
+    } else {
+      if (lane == 0) store_status(&status[tile], kAgg | (uint64_t)tot);
+      int64_t j = tile - 1;
+      uint32_t spins = 0;
+      bool failed = false;
+      for (;;) {
+        const int64_t t = j - lane;
+        uint64_t v = t >= 0 ? load_status(&status[t]) : kPre;  // nothing before tile 0
+        while (__ballot((v >> 62) == 0)) {
+          if (++spins > kLookbackSpins) {
+            failed = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          if ((v >> 62) == 0) v = load_status(&status[t]);
+        }
+        if (failed) break;
+        const unsigned long long pm = __ballot((v >> 62) == 2);
+        const int k = pm ? __ffsll((long long)pm) - 1 : 63;  // nearest tile with a prefix
+        int64_t mine = lane <= k ? (int64_t)(v & kCountMask) : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) mine += __shfl_xor(mine, o, 64);
+        before += mine;
+        if (pm) break;
+        j -= 64;
+      }
+      if (failed) {
+        if (lane == 0) atomicCAS(a.fail, 0, (int)FCT_ERR_HIP);
+        before = 0;
+      }
+      if (lane == 0) store_status(&status[tile], kPre | (uint64_t)(before + tot));
+    }
+    if (lane == 0) s_before = before;
+  }
+  __syncthreads();
+  const int64_t first = s_before;
+  if (tile == nb - 1 && threadIdx.x == 0) *a.S = first + tot;
+  int64_t pos = first + pre;
   while (m) {
     const int k = __ffs(m) - 1;
     m &= m - 1;
@@ -139,9 +197,9 @@ __global__ void __launch_bounds__(kSelThreads) select_write_kernel(SelectArgs a)
 
 hipError_t launch_select(const SelectArgs& a, hipStream_t st) {
   const int nb = select_grid(a.n);
-  hipLaunchKernelGGL(select_count_kernel, dim3(nb), dim3(kSelThreads), 0, st, a);
-  hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(1024), 0, st, a.counts, nb, a.offsets, a.S);
-  hipLaunchKernelGGL(select_write_kernel, dim3(nb), dim3(kSelThreads), 0, st, a);
+  hipLaunchKernelGGL(select_init_kernel, dim3((unsigned)((nb + 256) / 256)), dim3(256), 0, st,
+                     a.lookback, nb);
+  hipLaunchKernelGGL(select_kernel, dim3(nb), dim3(kSelThreads), 0, st, a, nb);
   return hipGetLastError();
 }
 
