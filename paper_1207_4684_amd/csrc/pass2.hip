@@ -39,6 +39,15 @@ template <> struct Load<Bf16> {
   }
 };
 
+// compare-exchange as a min and a max (v_min / v_max: no condition masks);
+// |.| values and the +inf padding are never NaN for finite data
+template <typename TA>
+__device__ __forceinline__ void cex(TA& a, TA& b) {
+  const TA lo = fmin(a, b), hi = fmax(a, b);
+  a = lo;
+  b = hi;
+}
+
 template <typename TA, int N>
 __device__ __forceinline__ void bitonic_sort(TA (&v)[N]) {
 #pragma unroll
@@ -49,14 +58,58 @@ __device__ __forceinline__ void bitonic_sort(TA (&v)[N]) {
       for (int i = 0; i < N; ++i) {
         const int l = i ^ j;
         if (l > i) {
-          const TA lo = v[i] < v[l] ? v[i] : v[l];
-          const TA hi = v[i] < v[l] ? v[l] : v[i];
-          if ((i & k) == 0) { v[i] = lo; v[l] = hi; }
-          else { v[i] = hi; v[l] = lo; }
+          if ((i & k) == 0) cex(v[i], v[l]);
+          else cex(v[l], v[i]);
         }
       }
     }
   }
+}
+
+// Sorts v[o .. o + 7] with the 19-comparator network of depth 6 (Knuth,
+// TAOCP vol. 3, section 5.3.4).
+template <int N>
+__device__ __forceinline__ void sort8(float (&v)[N], int o) {
+  cex(v[o + 0], v[o + 2]); cex(v[o + 1], v[o + 3]); cex(v[o + 4], v[o + 6]); cex(v[o + 5], v[o + 7]);
+  cex(v[o + 0], v[o + 4]); cex(v[o + 1], v[o + 5]); cex(v[o + 2], v[o + 6]); cex(v[o + 3], v[o + 7]);
+  cex(v[o + 0], v[o + 1]); cex(v[o + 2], v[o + 3]); cex(v[o + 4], v[o + 5]); cex(v[o + 6], v[o + 7]);
+  cex(v[o + 2], v[o + 4]); cex(v[o + 3], v[o + 5]);
+  cex(v[o + 1], v[o + 4]); cex(v[o + 3], v[o + 6]);
+  cex(v[o + 1], v[o + 2]); cex(v[o + 3], v[o + 4]); cex(v[o + 5], v[o + 6]);
+}
+
+// Median of |v[0]|, ..., |v[r2 - 1]| (r2 <= R2P; the rest of v is ignored):
+// the mean of the order statistics (r2 - 1) / 2 and r2 / 2 (0-based), as the
+// oracle forms it.
+// For r2 = 16 the two halves are sorted and the statistics 7 and 8 of their
+// union are min_i max(a_(i-1), b_(7-i)) and min_i max(a_(i-1), b_(8-i)) over
+// the splits i of the first 8 (9) values between the sorted halves a and b;
+// otherwise a bitonic sort and a uniform register index.
+template <int R2P>
+__device__ __forceinline__ float median_of(float (&v)[R2P], int r2) {
+  if (R2P == 16 && r2 == 16) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = fabsf(v[j]);
+    sort8(v, 0);
+    sort8(v, 8);
+    const float* a = v;
+    const float* b = v + 8;
+    float lo = fmin(b[7], a[7]);
+#pragma unroll
+    for (int i = 1; i < 8; ++i) lo = fmin(lo, fmax(a[i - 1], b[7 - i]));
+    float hi = fmax(a[0], b[7]);
+#pragma unroll
+    for (int i = 2; i < 9; ++i) hi = fmin(hi, fmax(a[i - 1], b[8 - i]));
+    return 0.5f * (lo + hi);
+  }
+#pragma unroll
+  for (int j = 0; j < R2P; ++j) v[j] = j < r2 ? fabsf(v[j]) : INFINITY;
+  bitonic_sort<float, R2P>(v);
+  typedef float fvec __attribute__((ext_vector_type(R2P)));
+  fvec w;
+#pragma unroll
+  for (int j = 0; j < R2P; ++j) w[j] = v[j];
+  return 0.5f * (w[(r2 - 1) >> 1] + w[r2 >> 1]);
 }
 
 __host__ __device__ int r2_padded(int r2) {
@@ -215,17 +268,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
       v[j + 2] = q4[2];
       v[j + 3] = q4[3];
     }
-#pragma unroll
-    for (int j = 0; j < R2P; ++j) v[j] = j < a.r2 ? fabsf(v[j]) : INFINITY;
-    bitonic_sort<float, R2P>(v);
-    const int k1 = (a.r2 - 1) >> 1, k2 = a.r2 >> 1;
-    float m1 = v[0], m2 = v[0];
-#pragma unroll
-    for (int j = 1; j < R2P; ++j) {
-      m1 = (j == k1) ? v[j] : m1;
-      m2 = (j == k2) ? v[j] : m2;
-    }
-    const float lam = 0.5f * (m1 + m2);
+    const float lam = median_of<R2P>(v, a.r2);
     const int64_t row = r0 + lane;
     if (row < a.n) {
       a.lambda[row] = lam;
@@ -325,17 +368,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
       v[j + 2] = q4[2];
       v[j + 3] = q4[3];
     }
-#pragma unroll
-    for (int j = 0; j < R2P; ++j) v[j] = j < a.r2 ? fabsf(v[j]) : INFINITY;
-    bitonic_sort<float, R2P>(v);
-    const int k1 = (a.r2 - 1) >> 1, k2 = a.r2 >> 1;
-    float m1 = v[0], m2 = v[0];
-#pragma unroll
-    for (int j = 1; j < R2P; ++j) {
-      m1 = (j == k1) ? v[j] : m1;
-      m2 = (j == k2) ? v[j] : m2;
-    }
-    const float lam = 0.5f * (m1 + m2);
+    const float lam = median_of<R2P>(v, a.r2);
     const int64_t row = r0 + lane;
     if (row < a.n) {
       a.lambda[row] = lam;
