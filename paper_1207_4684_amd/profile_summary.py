@@ -189,8 +189,9 @@ def main(argv=None):
                    help="substring of a kernel name; repeat to sum kernels launched together")
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--algorithmic-bytes", type=int, default=0)
-    t.add_argument("--copy-kernel", default="copy",
-                   help="substring naming the copy kernel of known size")
+    t.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer",
+                   help="substring naming the copy kernel of known size (the runtime's "
+                        "device-to-device copy by default; its largest dispatch is taken)")
     m = sub.add_parser("pmc")
     m.add_argument("fetch_db")
     m.add_argument("write_db")
