@@ -233,7 +233,14 @@ typedef struct {
   int64_t ld_lowp;
   int32_t d;           /* 1 <= d <= 64                                        */
   int32_t pad0;
-  fct_params prm;      /* as for l1_regress; s == 0: autotuned                */
+  fct_params prm;      /* as for l1_regress; s == 0: the library chooses s    */
+  /* optional device outputs of the instance's intermediate results (NULL:
+   * not written); they let a caller check or reuse each step */
+  double *R_out;       /* (d + 1) x (d + 1) column-major, the sketch's R     */
+  float *lambda_out;   /* n, the row-norm estimates of the sampling pass     */
+  int64_t *idx_out;    /* idx_cap entries: the first min(S, idx_cap) are the
+                        * kept rows, ascending                                */
+  int64_t idx_cap;
 } fct_instance;
 
 /*
@@ -246,9 +253,12 @@ typedef struct {
  * spread over four forked streams) and replayed on later calls with the same
  * instances, sizes and scratch; if capture is refused the sequence runs
  * eagerly.
- * Autotuning: for instances with prm.s == 0 the library times pass 1 for
- *   s in {64, 128, 256, 512} on the first instance of each (d, dt) class and
- *   keeps the fastest in the context (s_used reports it).
+ * Block size: for instances with prm.s == 0 the library takes the choice of
+ *   the paper's experiments for FCT1 (section "Numerical experiments"),
+ *   s = ceil(2 d ln d) rounded up to a power of two, at least 64 and at most
+ *   1024; s_used reports it.  The rule depends on d only, so the same batch
+ *   gets the same transform on every run and every device (s changes Pi1;
+ *   a choice by timing would not).
  * eps: default expected coreset size s_out = ceil(20 q / eps) when prm.s_out <= 0.
  * Outputs (host): x[off_i .. off_i + d_i) with off_i = sum_{k<i} d_k;
  *   obj, S, s_used, status: count entries each, any may be NULL except status.

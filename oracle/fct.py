@@ -66,7 +66,7 @@ def padded_rows(n: int, s: int) -> int:
 
 def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
               instance: int = 0, cauchy_one: bool = False, return_scale: bool = False,
-              row0: int = 0):
+              row0: int = 0, scale_per_column: bool = False):
     """Y = Pi1 X in FP64 for X of shape (n, q).
 
     ``cauchy_one`` replaces every Cauchy by 1 (used by conservation pins).
@@ -78,7 +78,9 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
     itself can cancel, and so can a single (H_s z)_t).
     ``row0`` (a multiple of s) places X as rows [row0, row0 + n) of a larger
     design: every random stream is indexed by the global row, so the results
-    of consecutive windows add up to Pi1 of their union.
+    of consecutive windows add up to Pi1 of their union.  With
+    ``scale_per_column`` the scale comes back before the max over j, as the
+    (r1, q) array of masses, which also adds up over windows.
     """
     if row0 % s:
         raise ValueError("row0 must be a multiple of s")
@@ -108,7 +110,7 @@ def pi1_apply(X, s: int, r1: int, seed: int, sign_flip: bool = True,
             S[:, col] = (np.bincount(hH, weights=4.0 * np.abs(cH) * absmass[:, col], minlength=r1)
                          + np.bincount(hI, weights=np.abs(gI), minlength=r1))
     if return_scale:
-        return Y, S.max(axis=1)
+        return Y, (S if scale_per_column else S.max(axis=1))
     return Y
 
 

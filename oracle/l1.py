@@ -29,11 +29,21 @@ import itertools
 import numpy as np
 
 
-def objective(A, b, x, w=None) -> float:
-    r = np.asarray(A, dtype=np.float64) @ np.asarray(x, dtype=np.float64) - np.asarray(b, dtype=np.float64)
-    if w is None:
-        return float(np.abs(r).sum())
-    return float((np.asarray(w, dtype=np.float64) * np.abs(r)).sum())
+def objective(A, b, x, w=None, chunk: int | None = None) -> float:
+    """sum_i w_i |A_i x - b_i| in FP64.  With ``chunk`` the rows are taken
+    ``chunk`` at a time (A may then be a large FP32 array or a transposed
+    view) and the chunk sums are added in row order."""
+    x = np.asarray(x, dtype=np.float64)
+    if chunk is None:
+        r = np.asarray(A, dtype=np.float64) @ x - np.asarray(b, dtype=np.float64)
+        if w is None:
+            return float(np.abs(r).sum())
+        return float((np.asarray(w, dtype=np.float64) * np.abs(r)).sum())
+    total = 0.0
+    for lo in range(0, A.shape[0], chunk):
+        hi = min(A.shape[0], lo + chunk)
+        total += objective(A[lo:hi], b[lo:hi], x, None if w is None else w[lo:hi])
+    return total
 
 
 def brute_force(A, b, w=None):

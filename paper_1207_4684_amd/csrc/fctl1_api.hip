@@ -7,7 +7,6 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
-#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -62,7 +61,6 @@ struct fct_ctx {
   size_t bpinned_bytes = 0;
   hipGraphExec_t bgraph = nullptr;
   std::vector<char> bsig;       // signature of the captured batch
-  std::map<int, int> tuned_s;   // (d << 1 | f64) -> FWHT block size
   void* noalloc = nullptr;      // this device's copy of g_noalloc_scratch (nullptr: lookup failed)
 };
 
@@ -718,10 +716,19 @@ int l1_sample_probs(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t
                             sum_lambda);
 }
 
+// Optional copies of an instance's intermediate results (batched form).
+struct CoresetOut {
+  double* R = nullptr;
+  float* lambda = nullptr;
+  int64_t* idx = nullptr;
+  int64_t idx_cap = 0;
+};
+
 static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d,
                         int64_t lda, fct_dtype dt, const void* A_lowp, const void* b_lowp,
                         int64_t ld_lowp, const fct_params* prm, int64_t cap, void* At, void* bt,
-                        double* w, int64_t* idx, int64_t* S_dev, Carve& cv) {
+                        double* w, int64_t* idx, int64_t* S_dev, Carve& cv,
+                        const CoresetOut* out = nullptr) {
   const int q = d + 1;
   const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
   int perr = 0;
@@ -753,6 +760,15 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
       return st;
   }
   HIP_TRY(launch_gather(A, b, lda, d, idx, S_dev, cap, At, bt, cap, dt == FCT_F64, c->stream));
+  if (out && out->R)
+    HIP_TRY(hipMemcpyAsync(out->R, R, (size_t)q * q * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (out && out->lambda)
+    HIP_TRY(hipMemcpyAsync(out->lambda, lam, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (out && out->idx && out->idx_cap > 0)
+    HIP_TRY(hipMemcpyAsync(out->idx, idx, (size_t)std::min(cap, out->idx_cap) * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, c->stream));
   return FCT_OK;
 }
 
@@ -952,6 +968,17 @@ struct BatchItem {
   size_t bytes;
 };
 
+// The FCT1 block size of the paper's experiments (section "Numerical
+// experiments"): ceil(2 d ln d), here rounded up to a power of two within
+// [64, 1024] (the butterflies work on powers of two; 64 keeps the blocks of
+// small d at the width of a wave).
+int batch_block_size(int d) {
+  const double t = std::ceil(2.0 * d * std::log((double)d));
+  int s = 64;
+  while (s < t && s < 1024) s <<= 1;
+  return s;
+}
+
 int batch_ensure_aux(fct_ctx* c, size_t pinned_bytes) {
   if (!c->branch[0]) {
     for (int k = 0; k < fct_ctx::kBranches; ++k) {
@@ -968,39 +995,6 @@ int batch_ensure_aux(fct_ctx* c, size_t pinned_bytes) {
     HIP_TRY(hipHostMalloc(&c->bpinned, pinned_bytes, hipHostMallocDefault));
     c->bpinned_bytes = pinned_bytes;
   }
-  return FCT_OK;
-}
-
-// Pass-1 time (ms) of one sketch of instance `in` with block size s.
-int time_sketch(fct_ctx* c, const fct_instance& in, fct_dtype dt, int s, float* ms) {
-  const int q = in.d + 1;
-  const int64_t n_pad = (in.n + s - 1) / s * s;
-  int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, s, in.prm.r1, esize(dt), in.prm.flags, &perr);
-  if (perr) return FCT_ERR_BAD_ARG;
-  Measure m;
-  carve_sketch(m, p, n_pad, q, in.prm.r1, esize(dt), false);
-  int st;
-  if ((st = ensure_scratch(c, m.off))) return st;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  float best = 1e30f;
-  for (int rep = 0; rep < 3; ++rep) {
-    Carve cv(c->scratch);
-    HIP_TRY(hipEventRecord(e0, c->stream));
-    if ((st = run_sketch(c, cv, in.A, in.n, in.d, in.lda, dt, in.b, s, in.prm.r1, in.prm.seed,
-                         in.prm.flags, nullptr, nullptr, nullptr, p)))
-      return st;
-    HIP_TRY(hipEventRecord(e1, c->stream));
-    HIP_TRY(hipEventSynchronize(e1));
-    float t = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    if (rep > 0 && t < best) best = t;  // the first run warms up
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  *ms = best;
   return FCT_OK;
 }
 
@@ -1031,8 +1025,13 @@ int batch_enqueue(fct_ctx* c, const fct_instance* inst, int count, fct_dtype dt,
     Carve rest(c->scratch);
     rest.off = cv.off;
     c->stream = c->branch[i % fct_ctx::kBranches];
+    CoresetOut out;
+    out.R = in.R_out;
+    out.lambda = in.lambda_out;
+    out.idx = in.idx_out;
+    out.idx_cap = in.idx_cap;
     st = coreset_impl(c, in.A, in.b, in.n, d, in.lda, dt, in.A_lowp, in.b_lowp, in.ld_lowp, &it.prm,
-                      it.cap, At, bt, w, idx, S_dev, rest);
+                      it.cap, At, bt, w, idx, S_dev, rest, &out);
     c->stream = main;
   }
   if (st) return st;
@@ -1079,28 +1078,7 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
   }
   for (int i = 0; i < count; ++i) {
     fct_params& prm = items[i].prm;
-    if (prm.s != 0) continue;
-    const int key = (inst[i].d << 1) | (dt == FCT_F64 ? 1 : 0);
-    auto hit = c->tuned_s.find(key);
-    if (hit == c->tuned_s.end()) {
-      int best_s = 256;
-      float best_t = 1e30f;
-      for (int s : {64, 128, 256, 512}) {
-        fct_params trial = prm;
-        trial.s = s;
-        if (check_params(&trial, inst[i].d + 1)) continue;
-        fct_instance probe = inst[i];
-        probe.prm = trial;
-        float t = 0.0f;
-        if ((st = time_sketch(c, probe, dt, s, &t))) return st;
-        if (t < best_t) {
-          best_t = t;
-          best_s = s;
-        }
-      }
-      hit = c->tuned_s.emplace(key, best_s).first;
-    }
-    prm.s = hit->second;
+    if (prm.s == 0) prm.s = batch_block_size(inst[i].d);
   }
   size_t total = 0;
   for (int i = 0; i < count; ++i) {

@@ -44,7 +44,8 @@ class fct_instance(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("A_lowp", ctypes.c_void_p),
                 ("b_lowp", ctypes.c_void_p), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
                 ("ld_lowp", ctypes.c_int64), ("d", ctypes.c_int32), ("pad0", ctypes.c_int32),
-                ("prm", fct_params)]
+                ("prm", fct_params), ("R_out", ctypes.c_void_p), ("lambda_out", ctypes.c_void_p),
+                ("idx_out", ctypes.c_void_p), ("idx_cap", ctypes.c_int64)]
 
 
 def _load():
@@ -305,8 +306,10 @@ def l1_select(ctx, lam, sum_lambda, s_out, seed, cap):
 def l1_regress_batched(ctx, items, eps=0.05):
     """Solve many instances in one batch (one captured graph).
 
-    items: dicts with A ((d, n) tensor), b, prm (fct_params; s = 0 autotunes)
-    and optionally A_lowp, b_lowp (BF16 copies).  Returns (results, status):
+    items: dicts with A ((d, n) tensor), b, prm (fct_params; s = 0: the
+    library's rule) and optionally A_lowp, b_lowp (BF16 copies) and the
+    device outputs R_out ((q, q) FP64, column-major), lambda_out ((n,) FP32)
+    and idx_out ((cap,) int64).  Returns (results, status):
     results[i] = dict(x, obj, S, s, status)."""
     count = len(items)
     arr = (fct_instance * count)()
@@ -315,9 +318,12 @@ def l1_regress_batched(ctx, items, eps=0.05):
         n, d, lda = _cm(it["A"])
         lo = it.get("A_lowp")
         ld_lo = _cm(lo)[2] if lo is not None else 0
+        io = it.get("idx_out")
         arr[i] = fct_instance(A=_ptr(it["A"]), b=_ptr(it["b"]), A_lowp=_ptr(lo),
                               b_lowp=_ptr(it.get("b_lowp")), n=n, lda=lda, ld_lowp=ld_lo, d=d,
-                              pad0=0, prm=it["prm"])
+                              pad0=0, prm=it["prm"], R_out=_ptr(it.get("R_out")),
+                              lambda_out=_ptr(it.get("lambda_out")), idx_out=_ptr(io),
+                              idx_cap=0 if io is None else int(io.numel()))
         t = _dt(it["A"])
         if dt is not None and t != dt:
             raise ValueError("all instances of a batch share one element type")

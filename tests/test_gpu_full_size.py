@@ -1,26 +1,31 @@
-"""GPU parity at the full sizes of the benchmark workloads, on outputs the
-oracle can compute piece by piece.
+"""GPU parity at the full sizes of the benchmark workloads against the oracle.
 
-* tall (4,194,304 x 32 FP32; the benchmark's workload): lambda on sampled
-  rows for the FP32 and BF16 passes, the selection over all rows given the
-  GPU's lambda, and the (1 + eps) objective of both paths against a
-  weak-duality lower bound.
-* precision (33,554,432 x 64 FP32 + BF16 copy) and large (268,435,456 x 16
-  FP32): the sketch of one window of rows against the oracle (the streams
-  are indexed by global row), the whole sketch against the sum of window
-  sketches, R against the sketch it factors, sampled lambda, the selection
-  in a window of rows, and the (1 + eps) objective.
+* The whole sketch Y = Pi1 [A, -b] of tall (4,194,304 x 32), precision
+  (33,554,432 x 64) and large (268,435,456 x 16), element by element against
+  the oracle's, stored in tests/golden/ by make_full_sketches.py (oracle and
+  synth only), gated at 1e-5 of each row's l1 mass; R against the oracle's
+  Gram matrix of that sketch.
+* lambda on sampled rows for the FP32 and BF16 passes (the oracle evaluates
+  those rows from the GPU's R), and the selection given the GPU's lambda
+  (over all rows, or a window of rows).
+* The (1 + eps) objective of the plain and BF16 regressions: f(x) is the
+  oracle's FP64 host sum, and the optimum is bounded below by the oracle's
+  weak-duality certificate.
 
 The oracle never sees the GPU's outputs as expected values: it recomputes
 each checked quantity from the same input bytes (and, for lambda and the
 selection, from the GPU's R or lambda where the check is of the next step).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import synth
-from oracle import basis, fct, l1, lowp, philox, sampling
+from oracle import basis, l1, lowp, philox, sampling
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -112,21 +117,44 @@ def check_one_plus_eps(F, ctx, L):
     prm = F.params(s=w.s, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
     x_plain, _, _ = F.l1_regress(ctx, L.Ad, L.bd, prm, eps=w.eps)
     x_bf16, _, _ = F.l1_regress(ctx, L.Ad, L.bd, prm, eps=w.eps, A_lowp=L.Al, b_lowp=L.bl)
-    fs = {name: float(F.fct_l1_objective(ctx, L.Ad, L.bd, x))
+    # f(x) by the oracle: an FP64 host sum over the input bytes
+    fs = {name: l1.objective(L.A.T, L.b, x, chunk=1 << 22)
           for name, x in (("plain", x_plain), ("bf16", x_bf16))}
     print(f"{w.name}: regressions done {fs}", flush=True)
     # a candidate optimum from the all-rows solver; the oracle's dual bound is
     # valid whoever produced the candidate
     x0, _ = F.l1_solve(ctx, L.Ad, L.bd, torch.ones(w.n, dtype=torch.float64, device="cuda"), iters=120)
-    f0 = float(F.fct_l1_objective(ctx, L.Ad, L.bd, x0))
-    print(f"{w.name}: all-rows candidate {f0}", flush=True)
     need = max(fs.values()) / (1 + 0.5 * w.eps)   # a bound this high settles both claims
     lower = l1.dual_lower_bound(L.A.T, L.b, x0, threads=16, stop_at=need)
-    print(f"{w.name}: all-rows candidate f / lower bound = {f0 / lower:.9f}", flush=True)
+    print(f"{w.name}: lower bound {lower}", flush=True)
     assert lower > 0
     for name, f in fs.items():
         print(f"{w.name} {name}: f / lower bound = {f / lower:.9f}")
         assert f <= (1 + w.eps) * lower, (name, f / lower)
+
+
+def check_whole_sketch(F, ctx, L):
+    """The whole sketch against the oracle's, and R against the oracle's
+    Gram matrix of it."""
+    w = L.w
+    Yo = np.load(os.path.join(GOLDEN, f"sketch_{w.name}.npy"))
+    S = np.load(os.path.join(GOLDEN, f"scale_{w.name}.npy"))
+    Y, R = F.fct_sketch(ctx, L.Ad, L.bd, w.s, w.r1, w.seed)
+    Yg = host(Y).astype(np.float64)
+    err = np.max(np.abs(Yg - Yo), axis=1)
+    print(f"{w.name}: whole sketch max err / S = {float(np.max(err / S)):.3e}", flush=True)
+    assert np.all(err <= 1e-5 * S), float(np.max(err / S))
+    # R^T R = Y^T Y for the FP64 sketch R was taken from, which is within
+    # 1e-5 S_i of the oracle's row by row: |d(Y^T Y)_jk| <= 1e-5 sum_i S_i
+    # (|Y_ij| + |Y_ik|) + (1e-5)^2 sum_i S_i^2, plus the QR's rounding
+    Rg = host(R)
+    assert np.all(np.diag(Rg) > 0) and np.allclose(np.tril(Rg, -1), 0)
+    G = Yo.T @ Yo
+    aY = S[:, None] * np.abs(Yo)
+    bound = 1e-5 * (aY.sum(axis=0)[:, None] + aY.sum(axis=0)[None, :]) + 1e-10 * float(S @ S)
+    bound += 1e-12 * np.abs(G).max()
+    assert np.all(np.abs(Rg.T @ Rg - G) <= bound), float(np.max(np.abs(Rg.T @ Rg - G) / bound))
+    return R
 
 
 # ---- tall ------------------------------------------------------------------
@@ -138,9 +166,8 @@ def tall(F, ctx):
     L.close()
 
 
-def test_tall_full_size_lambda_and_selection(F, ctx, tall):
-    w = tall.w
-    _, R = F.fct_sketch(ctx, tall.Ad, tall.bd, w.s, w.r1, w.seed, want_y=False)
+def test_tall_full_size_sketch_lambda_selection(F, ctx, tall):
+    R = check_whole_sketch(F, ctx, tall)
     lam, tot = check_lambda_sampled(F, ctx, tall, R, np.random.default_rng(1))
     check_selection(F, ctx, tall, lam, tot)
 
@@ -151,39 +178,6 @@ def test_tall_full_size_one_plus_eps(F, ctx, tall):
 
 # ---- precision and large ---------------------------------------------------
 
-def check_windows_and_basis(F, ctx, L, win_rows, oracle_row0):
-    """Window sketch vs the oracle, the whole sketch vs the sum of windows, R vs Y."""
-    w = L.w
-    n = w.n
-    q = w.d + 1
-    Y, R = F.fct_sketch(ctx, L.Ad, L.bd, w.s, w.r1, w.seed)
-    Yg = host(Y).astype(np.float64)
-    total = np.zeros_like(Yg)
-    absum = np.zeros_like(Yg)
-    starts = list(range(0, n, win_rows))
-    for a in starts:
-        bnd = min(n, a + win_rows)
-        Yw = host(F.fct_sketch_window(ctx, L.Ad[:, a:bnd], L.bd[a:bnd], w.s, w.r1, w.seed, a)).astype(np.float64)
-        total += Yw
-        absum += np.abs(Yw)
-    # one window of 2^20 rows inside the design against the oracle
-    a, bnd = oracle_row0, oracle_row0 + (1 << 20)
-    Yw = host(F.fct_sketch_window(ctx, L.Ad[:, a:bnd], L.bd[a:bnd], w.s, w.r1, w.seed, a)).astype(np.float64)
-    Yo, S = fct.pi1_apply(L.rows(np.arange(a, bnd)), w.s, w.r1, w.seed, return_scale=True, row0=a)
-    err = np.max(np.abs(Yw - Yo), axis=1)
-    assert np.all(err <= 1e-5 * S), float(np.max(err / S))
-    # partial sums are rounded to FP32 once per row range: a few ulp of the
-    # summed magnitudes
-    assert np.all(np.abs(Yg - total) <= 1e-5 * absum.max(axis=1, keepdims=True))
-    # R factors the sketch: R^T R = Y^T Y (Y here is the FP32 rounding of the
-    # FP64 sketch R was computed from)
-    Rg = host(R)
-    G = Yg.T @ Yg
-    assert np.all(np.diag(Rg) > 0) and np.allclose(np.tril(Rg, -1), 0)
-    assert np.max(np.abs(Rg.T @ Rg - G)) <= 1e-5 * np.abs(G).max()
-    return R
-
-
 @pytest.fixture(scope="module")
 def precision(F, ctx):
     L = Loaded(F, ctx, synth.PRECISION)
@@ -192,7 +186,7 @@ def precision(F, ctx):
 
 
 def test_precision_full_size_sketch_lambda_selection(F, ctx, precision):
-    R = check_windows_and_basis(F, ctx, precision, 1 << 23, 5 << 22)
+    R = check_whole_sketch(F, ctx, precision)
     lam, tot = check_lambda_sampled(F, ctx, precision, R, np.random.default_rng(2))
     check_selection(F, ctx, precision, lam, tot, window=(1 << 24, (1 << 24) + (1 << 22)))
 
@@ -209,7 +203,7 @@ def large(F, ctx):
 
 
 def test_large_full_size_sketch_lambda_selection(F, ctx, large):
-    R = check_windows_and_basis(F, ctx, large, 1 << 26, 37 << 22)
+    R = check_whole_sketch(F, ctx, large)
     lam, tot = check_lambda_sampled(F, ctx, large, R, np.random.default_rng(3))
     check_selection(F, ctx, large, lam, tot, window=(3 << 26, (3 << 26) + (1 << 22)))
 
