@@ -287,6 +287,29 @@ int l1_select(fct_ctx *ctx, const float *lambda, const double *sum_lambda, int64
 
 /* ---- supporting calls (diagnostics and data preparation) ---------------- */
 
+/*
+ * fct_lowp_residual: the residual form of the design for the BF16 sampling
+ * pass.  The row-norm estimates of the regression figure's steps 4-5 depend
+ * on X only through X R^-1, which a change of basis T leaves alone:
+ * (X T)(R T)^-1 = X R^-1.  With T = [I x0; 0 1] and x0 the least-squares
+ * solution of the sketched problem (R_AA x0 = -r_Ab for R = [R_AA r_Ab;
+ * 0 r_bb], the R of fct_sketch with b), X T = [A, -r0] with r0 = b - A x0:
+ * the column rounded to BF16 then carries the residual, usually far smaller
+ * than b, so its rounding error shrinks with it.  Pass the BF16 copy of A,
+ * r_lowp as its b, and R_res as R to l1_sample_probs (l1_regress forms its
+ * own R and does not take this form).
+ *   A, b: device, column-major n x d and n, element type dt (F32 or F64).
+ *   R: device FP64 (d+1) x (d+1), column-major, from fct_sketch with b.
+ *   r_lowp: device BF16 [n]: r0 formed in FP64, rounded to FP32 and then to
+ *     the nearest BF16 (ties to even).
+ *   R_res: device FP64 (d+1) x (d+1), column-major: R T, its last column
+ *     R_AA x0 + r_Ab formed explicitly (zero up to rounding).
+ * d <= 64.  Enqueued on the context's stream; no synchronization.
+ */
+int fct_lowp_residual(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d,
+                      int64_t lda, fct_dtype dt, const double *R, uint16_t *r_lowp,
+                      double *R_res);
+
 /* words: device uint32 [4 * count], the Philox4x32-10 words of calls
  * idx0 .. idx0 + count - 1 of `stream` (0..3) under `seed`, instance 0. */
 int fct_rng_words(fct_ctx *ctx, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,

@@ -177,6 +177,10 @@ hipError_t launch_irls(const void* At, const void* bt, const double* w, const in
                        hipStream_t st, int rows_override = 0, int wgs_override = 0);
 
 hipError_t launch_to_bf16(const float* x, int64_t count, uint16_t* y, hipStream_t st);
+// x0 = -R_AA^-1 r_Ab, R_res = R T and the BF16 residual r0 = b - A x0.
+hipError_t launch_lowp_residual(const void* A, const void* b, int64_t lda, int64_t n, int d,
+                                bool f64, const double* R, double* x0, double* R_res, uint16_t* r,
+                                hipStream_t st);
 hipError_t launch_l1_objective(const void* A, const void* b, int64_t lda, int64_t n, int d,
                                const double* x, bool f64, double* parts, int nparts, double* out,
                                hipStream_t st);

@@ -1242,6 +1242,21 @@ int fct_to_bf16(fct_ctx* c, const float* x, int64_t count, uint16_t* y) {
   return FCT_OK;
 }
 
+int fct_lowp_residual(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+                      fct_dtype dt, const double* R, uint16_t* r_lowp, double* R_res) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!b || !R || !r_lowp || !R_res || d > 64 || (dt != FCT_F32 && dt != FCT_F64))
+    return FCT_ERR_BAD_ARG;
+  Measure m;
+  m.take<double>(64);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  double* x0 = cv.take<double>(64);
+  HIP_TRY(launch_lowp_residual(A, b, lda, n, d, dt == FCT_F64, R, x0, R_res, r_lowp, c->stream));
+  return FCT_OK;
+}
+
 int fct_l1_objective(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
                      fct_dtype dt, const double* x, double* out) {
   int st = check_common(c, A, n, d, lda);

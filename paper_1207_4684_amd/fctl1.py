@@ -79,6 +79,7 @@ def _load():
         "fct_pi1_streams": (ctypes.c_int, [P, U64, I32, I32, U64, I64, P, P, P, P, P]),
         "fct_fwht": (ctypes.c_int, [P, P, I64, I32]),
         "fct_to_bf16": (ctypes.c_int, [P, P, I64, P]),
+        "fct_lowp_residual": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, P]),
         "fct_l1_objective": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, PD, PD]),
         "l1_solve": (ctypes.c_int, [P, P, P, P, I64, I32, I64, ctypes.c_int, I32, PD, PD]),
         "l1_select": (ctypes.c_int, [P, P, P, I64, I64, U64, I64, P, P, PI64]),
@@ -98,9 +99,9 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream", "fct_sketch",
-            "fct_sketch_window",
-            "l1_sample_probs", "l1_sample_probs_ex", "l1_sample_probs_noalloc", "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams",
-            "fct_fwht", "fct_to_bf16", "fct_l1_objective", "l1_solve", "l1_select",
+            "fct_sketch_window", "l1_sample_probs", "l1_sample_probs_ex", "l1_sample_probs_noalloc",
+            "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams", "fct_fwht",
+            "fct_to_bf16", "fct_lowp_residual", "fct_l1_objective", "l1_solve", "l1_select",
             "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option")
 
 
@@ -385,6 +386,19 @@ def fct_to_bf16(ctx, x):
     y = torch.empty(x.shape, dtype=torch.int16, device=x.device)
     _check(ctx.call(_lib.fct_to_bf16, ctx.handle, _ptr(x.contiguous()), x.numel(), _ptr(y)), "fct_to_bf16")
     return y
+
+
+def fct_lowp_residual(ctx, A, b, R):
+    """(r_lowp, R_res): the BF16 residual column b - A x0 (int16 storage) and
+    the q x q view of R T for the BF16 sampling pass on [A_lowp, -r0]."""
+    n, d, lda = _cm(A)
+    q = d + 1
+    Rbuf = R.t().contiguous()
+    r = torch.empty(n, dtype=torch.int16, device=A.device)
+    Rres = torch.empty((q, q), dtype=torch.float64, device=A.device)
+    _check(ctx.call(_lib.fct_lowp_residual, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A),
+                    _ptr(Rbuf), _ptr(r), _ptr(Rres)), "fct_lowp_residual")
+    return r, Rres.t()
 
 
 def fct_l1_objective(ctx, A, b, x):

@@ -8,7 +8,8 @@
 * lambda on sampled rows for the FP32 and BF16 passes (the oracle evaluates
   those rows from the GPU's R), and the selection given the GPU's lambda
   (over all rows, or a window of rows).
-* The (1 + eps) objective of the plain and BF16 regressions: f(x) is the
+* The (1 + eps) objective of the plain and BF16 regressions (and, on tall
+  and large, of the optimized regression with Gaussian Pi2): f(x) is the
   oracle's FP64 host sum, and the optimum is bounded below by the oracle's
   weak-duality certificate.
 
@@ -112,14 +113,19 @@ def check_selection(F, ctx, L, lam, tot, window=None):
     assert np.array_equal(gw[sel], 1.0 / p[oidx - lo])
 
 
-def check_one_plus_eps(F, ctx, L):
+def check_one_plus_eps(F, ctx, L, optimized=False):
+    """(1 + eps) of the plain and BF16 regressions, and with ``optimized`` of
+    the optimized regression (Gaussian Pi2, r2 = 8)."""
     w = L.w
     prm = F.params(s=w.s, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
-    x_plain, _, _ = F.l1_regress(ctx, L.Ad, L.bd, prm, eps=w.eps)
-    x_bf16, _, _ = F.l1_regress(ctx, L.Ad, L.bd, prm, eps=w.eps, A_lowp=L.Al, b_lowp=L.bl)
+    xs = {"plain": F.l1_regress(ctx, L.Ad, L.bd, prm, eps=w.eps)[0],
+          "bf16": F.l1_regress(ctx, L.Ad, L.bd, prm, eps=w.eps, A_lowp=L.Al, b_lowp=L.bl)[0]}
+    if optimized:
+        po = F.params(s=w.s, r1=w.r1, r2=8, s_out=w.s_out, seed=w.seed,
+                      flags=F.FCT_FLAG_GAUSSIAN_PI2)
+        xs["optimized"] = F.l1_regress(ctx, L.Ad, L.bd, po, eps=w.eps)[0]
     # f(x) by the oracle: an FP64 host sum over the input bytes
-    fs = {name: l1.objective(L.A.T, L.b, x, chunk=1 << 22)
-          for name, x in (("plain", x_plain), ("bf16", x_bf16))}
+    fs = {name: l1.objective(L.A.T, L.b, x, chunk=1 << 22) for name, x in xs.items()}
     print(f"{w.name}: regressions done {fs}", flush=True)
     # a candidate optimum from the all-rows solver; the oracle's dual bound is
     # valid whoever produced the candidate
@@ -173,7 +179,7 @@ def test_tall_full_size_sketch_lambda_selection(F, ctx, tall):
 
 
 def test_tall_full_size_one_plus_eps(F, ctx, tall):
-    check_one_plus_eps(F, ctx, tall)
+    check_one_plus_eps(F, ctx, tall, optimized=True)
 
 
 # ---- precision and large ---------------------------------------------------
@@ -209,4 +215,4 @@ def test_large_full_size_sketch_lambda_selection(F, ctx, large):
 
 
 def test_large_full_size_one_plus_eps(F, ctx, large):
-    check_one_plus_eps(F, ctx, large)
+    check_one_plus_eps(F, ctx, large, optimized=True)

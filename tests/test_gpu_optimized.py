@@ -95,7 +95,7 @@ def test_optimized_regress_one_plus_eps(F, ctx, name, n, r2, eps):
                    flags=F.FCT_FLAG_GAUSSIAN_PI2)
     x, obj, S = F.l1_regress(ctx, dev(A), dev(b), prm, eps=eps)
     At64, b64 = A.T.astype(np.float64), b.astype(np.float64)
-    if n <= 70000:
+    if n <= 20000:
         fopt = l1.lp(At64, b64)[1]
     else:
         x0, _ = F.l1_solve(ctx, dev(At64.T), dev(b64), dev(np.ones(n)), iters=120)
