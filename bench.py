@@ -329,38 +329,51 @@ def bf16_error_report(F, torch, ctx, w, Ad, bd, Al, bl):
     """The BF16 sampling pass against the library's FP64 pass 2 on the same R
     (X promoted to FP64 on the device): the distribution of lambda_bf16 /
     lambda_64, the largest relative error of p, and the overlap of the
-    selected rows with the FP32 and FP64 selections (same seed)."""
+    selected rows with the FP32 and FP64 selections (same seed); for the
+    plain form [A_bf16, -b_bf16] with R and for the residual form
+    [A_bf16, -r0_bf16] with R T (fct_lowp_residual)."""
     _, R = F.fct_sketch(ctx, Ad, bd, w.s, w.r1, w.seed, want_y=False)
     lam32, p32, t32 = F.l1_sample_probs(ctx, Ad, bd, R, w.r2, w.seed, w.s_out)
-    lamb, pb, tb = F.l1_sample_probs(ctx, Al, bl, R, w.r2, w.seed, w.s_out)
     A64, b64 = Ad.double(), bd.double()
     lam64, p64, t64 = F.l1_sample_probs(ctx, A64, b64, R, w.r2, w.seed, w.s_out)
     del A64, b64
     torch.cuda.empty_cache()
-    ratio = (lamb.double() / lam64.double())[lam64 > 0]
-    qs = torch.quantile(ratio[:: max(1, ratio.numel() // (1 << 24))],
-                        torch.tensor([0.01, 0.5, 0.99], dtype=torch.float64, device="cuda"))
-    inside = ((ratio >= 0.5) & (ratio <= 1.5)).double().mean()
-    pm = p64.double() > 0
-    prel = ((pb.double() - p64.double()).abs() / p64.double())[pm].max()
     cap = 4 * w.s_out + 1024
-    i32, _, _ = F.l1_select(ctx, lam32, t32, w.s_out, w.seed, cap)
-    ib, _, _ = F.l1_select(ctx, lamb, tb, w.s_out, w.seed, cap)
-    i64, _, _ = F.l1_select(ctx, lam64, t64, w.s_out, w.seed, cap)
-    i32, ib, i64 = i32.cpu().numpy(), ib.cpu().numpy(), i64.cpu().numpy()
-    return {"reference": "library FP64 pass 2 (FP64 data and M) on the same R",
-            "lambda_ratio_p01_p50_p99": [round(float(v), 5) for v in qs.tolist()],
-            "lambda_ratio_frac_in_half_to_three_halves": round(float(inside), 6),
-            "p_max_rel_err": float(prel),
-            "sum_lambda_rel_err": float(abs(tb.item() / t64.item() - 1)),
-            "jaccard_idx_bf16_vs_f32": round(jaccard(ib, i32), 5),
-            "jaccard_idx_bf16_vs_f64": round(jaccard(ib, i64), 5),
-            "jaccard_idx_f32_vs_f64": round(jaccard(i32, i64), 5)}
+    i32 = F.l1_select(ctx, lam32, t32, w.s_out, w.seed, cap)[0].cpu().numpy()
+    i64 = F.l1_select(ctx, lam64, t64, w.s_out, w.seed, cap)[0].cpu().numpy()
+
+    def figures(lamb, pb, tb):
+        ratio = (lamb.double() / lam64.double())[lam64 > 0]
+        qs = torch.quantile(ratio[:: max(1, ratio.numel() // (1 << 24))],
+                            torch.tensor([0.01, 0.5, 0.99], dtype=torch.float64, device="cuda"))
+        inside = ((ratio >= 0.5) & (ratio <= 1.5)).double().mean()
+        pm = p64.double() > 0
+        prel = ((pb.double() - p64.double()).abs() / p64.double())[pm].max()
+        ib = F.l1_select(ctx, lamb, tb, w.s_out, w.seed, cap)[0].cpu().numpy()
+        return {"lambda_ratio_p01_p50_p99": [round(float(v), 5) for v in qs.tolist()],
+                "lambda_ratio_frac_in_half_to_three_halves": round(float(inside), 6),
+                "p_max_rel_err": float(prel),
+                "sum_lambda_rel_err": float(abs(tb.item() / t64.item() - 1)),
+                "jaccard_idx_bf16_vs_f32": round(jaccard(ib, i32), 5),
+                "jaccard_idx_bf16_vs_f64": round(jaccard(ib, i64), 5)}
+
+    out = {"reference": "library FP64 pass 2 (FP64 data and M) on the same R"}
+    out.update(figures(*F.l1_sample_probs(ctx, Al, bl, R, w.r2, w.seed, w.s_out)))
+    out["jaccard_idx_f32_vs_f64"] = round(jaccard(i32, i64), 5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r_lowp, Rres = F.fct_lowp_residual(ctx, Ad, bd, R)
+    e1.record()
+    torch.cuda.synchronize()
+    res = figures(*F.l1_sample_probs(ctx, Al, r_lowp, Rres, w.r2, w.seed, w.s_out))
+    res["residual_column_ms"] = round(e0.elapsed_time(e1), 4)
+    out["residual_form"] = res
+    return out
 
 
 def bench_batched(F, ctx, count: int, steps: int):
     """The batching workload: `count` instances of uneven n and d solved in one
-    batch (captured graph, block size s autotuned per d), against the same
+    batch (captured graph, block size s from the library's rule per d), against the same
     instances solved one after another by the single-instance path with the
     block sizes the tuner chose."""
     import torch
@@ -378,7 +391,7 @@ def bench_batched(F, ctx, count: int, steps: int):
     rows = sum(w.n for w in ws)
     nbytes = sum(2 * w.n * (w.d + 1) * 4 + w.n * 4 for w in ws)
     t0 = time.perf_counter()
-    res, st = F.l1_regress_batched(ctx, items, eps=0.05)   # autotunes s and captures the graph
+    res, st = F.l1_regress_batched(ctx, items, eps=0.05)   # chooses s and captures the graph
     t_first = time.perf_counter() - t0
     if st != 0:
         bad = [(it["w"].seed, it["w"].n, it["w"].d, r["s"], r["status"])
@@ -419,7 +432,7 @@ def bench_batched(F, ctx, count: int, steps: int):
         "batched_rows_per_s": round(rows / dt_batch), "sequential_rows_per_s": round(rows / dt_seq),
         "batched_GBps": round(nbytes / dt_batch / 1e9, 1),
         "batched_hbm_frac": round(nbytes / dt_batch / 1e9 / HBM_PEAK_GBS, 4),
-        "first_call_s": round(t_first, 3), "autotuned_s_by_d": tuned,
+        "first_call_s": round(t_first, 3), "block_size_by_d": tuned,
         "same_coreset_sizes": same_S, "max_objective_deviation_batched_vs_single": dev,
     }
 

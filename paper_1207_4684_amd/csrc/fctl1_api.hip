@@ -1062,7 +1062,7 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
   int st;
   std::vector<BatchItem> items((size_t)count);
   const size_t es = esize(dt);
-  // arguments, autotuning, sizes
+  // arguments, block sizes, sizes
   for (int i = 0; i < count; ++i) {
     const fct_instance& in = inst[i];
     if ((st = check_common(c, in.A, in.n, in.d, in.lda))) return st;

@@ -46,11 +46,11 @@ def capacity(w):
     return min(w.n, 2 * w.s_out + 8 * int(math.sqrt(w.s_out)) + 1024)
 
 
-def make_batch(F, count, autotune_every=2, outputs=False):
+def make_batch(F, count, library_s_every=2, outputs=False):
     items, hosts = [], []
     for i, w in enumerate(synth.batch_instances(count)):
         A, b, _ = synth.generate(w)
-        s = 0 if i % autotune_every == 0 else w.s
+        s = 0 if i % library_s_every == 0 else w.s
         prm = F.params(s=s, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
         it = dict(A=torch.from_numpy(A).cuda(), b=torch.from_numpy(b).cuda(), prm=prm, w=w)
         if outputs:
