@@ -5,7 +5,7 @@
 // Row i is kept iff its stream-3 word w_i satisfies w_i < floor(p_i 2^32),
 // with p_i formed in FP64 (the event "uniform < p_i" on the 2^-32 grid).
 // Kept rows are listed in ascending order by one pass over lambda: a
-// workgroup takes the next 4096-row tile from a ticket counter, decides its
+// workgroup takes the next 8192-row tile from a ticket counter, decides its
 // rows, publishes its count, and finds the count of all earlier tiles by
 // looking back over their published counts and prefixes (a decoupled
 // look-back scan); then it writes its rows at that offset after an in-tile
@@ -18,7 +18,7 @@
 namespace fctl1 {
 
 static constexpr int kSelThreads = 256;
-static constexpr int kSelRowsPerThread = 16;
+static constexpr int kSelRowsPerThread = 32;
 static constexpr int kSelRows = kSelThreads * kSelRowsPerThread;
 
 int select_grid(int64_t n) { return (int)((n + kSelRows - 1) / kSelRows); }
@@ -31,8 +31,13 @@ __device__ __forceinline__ uint64_t threshold(float lam, double s_out, double to
   return (uint64_t)(t < 4294967296.0 ? t : 4294967296.0);
 }
 
-// keep mask of this thread's 16 consecutive rows (bit k = row base + k);
-// base is a multiple of 16, so a whole group is four 16-byte loads
+// Keep mask of this thread's 32 consecutive rows (bit k = row base + k);
+// base is a multiple of 32, so a whole group is eight 16-byte loads.  The
+// decision w < floor(p 2^32) holds iff the unfloored p 2^32 >= w + 1.  That
+// value is first estimated as lambda * (s_out 2^32 / sum lambda), within a few
+// units of 2^-53 of it; the estimate settles the decision unless it lies
+// within a relative 1e-12 of w + 1, and only those rare rows (and every row
+// when p is written out) evaluate p itself as the oracle does.
 __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base, double total,
                                               bool write_p) {
   float lam[kSelRowsPerThread];
@@ -50,6 +55,8 @@ __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base,
 #pragma unroll
     for (int k = 0; k < kSelRowsPerThread; ++k) lam[k] = base + k < a.n ? a.lambda[base + k] : 0.0f;
   }
+  const bool quick = !write_p && total > 0.0;
+  const double scale = quick ? a.s_out * 4294967296.0 / total : 0.0;
   uint32_t mask = 0;
 #pragma unroll
   for (int qd = 0; qd < kSelRowsPerThread / 4; ++qd) {
@@ -61,10 +68,18 @@ __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base,
     for (int k = 0; k < 4; ++k) {
       const int64_t i = r0 + k;
       if (i < a.n) {
-        double p;
-        const uint64_t t = threshold(lam[4 * qd + k], a.s_out, total, &p);
-        if (write_p && a.p_out) a.p_out[i] = (float)p;
-        if ((uint64_t)ws[k] < t) mask |= 1u << (4 * qd + k);
+        const double need = (double)ws[k] + 1.0;
+        const double est = (double)lam[4 * qd + k] * scale;
+        bool keep;
+        if (quick && (est > need * (1.0 + 1e-12) || est < need * (1.0 - 1e-12))) {
+          keep = est > need;
+        } else {
+          double p;
+          const uint64_t t = threshold(lam[4 * qd + k], a.s_out, total, &p);
+          if (write_p && a.p_out) a.p_out[i] = (float)p;
+          keep = (uint64_t)ws[k] < t;
+        }
+        if (keep) mask |= 1u << (4 * qd + k);
       }
     }
   }

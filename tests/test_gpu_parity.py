@@ -332,3 +332,37 @@ def test_regress_one_plus_eps(F, ctx, name, n, eps):
     assert f <= (1 + eps) * fopt, f / fopt
     # the device objective agrees with the host one
     assert np.isclose(F.fct_l1_objective(ctx, dev(A), dev(b), x), f, rtol=1e-9)
+
+
+def test_argument_checks_with_a_real_context(F, ctx):
+    """The argument checks behind the context check: a misaligned window
+    start, an empty batch, ldat < S and cap < 1 are FCT_ERR_BAD_ARG with a
+    live context and live buffers, and leave the context usable."""
+    import ctypes
+    lib = F._lib
+    h = ctx.handle
+    A = torch.zeros((4, 1024), dtype=torch.float32, device="cuda")
+    b = torch.zeros(1024, dtype=torch.float32, device="cuda")
+    Y = torch.zeros((5, 64), dtype=torch.float32, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    # row0 not a multiple of s (64), and not of 256
+    assert lib.fct_sketch_window(h, P(A), 1024, 4, 1024, F.FCT_F32, P(b), 64, 64, 1, 32, 0, P(Y)) == -1
+    assert lib.fct_sketch_window(h, P(A), 1024, 4, 1024, F.FCT_F32, P(b), 64, 64, 1, 128, 0, P(Y)) == -1
+    # an empty batch
+    inst = (F.fct_instance * 1)()
+    x = (ctypes.c_double * 8)()
+    status = (ctypes.c_int32 * 1)()
+    assert lib.l1_regress_batched(h, inst, 0, F.FCT_F32, 0.05, x, None, None, None, status) == -1
+    # ldat < S
+    w = torch.ones(1024, dtype=torch.float64, device="cuda")
+    assert lib.l1_solve(h, P(A), P(b), P(w), 1024, 4, 512, F.FCT_F32, 0, x, None) == -1
+    # cap < 1
+    lam = torch.ones(1024, dtype=torch.float32, device="cuda")
+    tot = torch.ones(1, dtype=torch.float64, device="cuda")
+    idx = torch.zeros(8, dtype=torch.int64, device="cuda")
+    S = ctypes.c_int64()
+    assert lib.l1_select(h, P(lam), P(tot), 1024, 10, 0, 0, P(idx), P(w), ctypes.byref(S)) == -1
+    # the context still works
+    Yv, _ = F.fct_sketch(ctx, A, b, 64, 64, 1, want_r=False)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(Yv).item() == 0
