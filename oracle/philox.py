@@ -28,7 +28,10 @@ written description): key = (seed mod 2^32, seed >> 32); counter =
 * stream 2, idx = a * r2 + c: word w0 gives the Cauchy Pi2[a, c]; for the
   optimized regression (Gaussian Pi2) words (w0, w1) give the Gaussian
   Pi2[a, c] by the Box-Muller transform.
-* stream 3, idx = i >> 2: word (i & 3) is the uniform that decides row i.
+* stream 3, idx = i >> 2: word (i & 3) is the uniform that decides row i
+  (instance k: the k-th of several independent draws from one sampling pass).
+* stream 4, idx = j >> 2: word (j & 3) is the uniform of sample j of a draw
+  with replacement (instance k: the k-th draw).
 
 Pinned by ``tests/test_oracle_rng.py`` against an independent implementation
 (rocRAND's Philox4x32-10 engine, compiled on the host) and by distribution
@@ -48,6 +51,7 @@ STREAM_PI1 = 0
 STREAM_SIGN = 1
 STREAM_PI2 = 2
 STREAM_SAMPLE = 3
+STREAM_REPLACE = 4
 
 
 def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
@@ -180,3 +184,11 @@ def sample_words(seed: int, n: int, instance: int = 0, start: int = 0):
     ncalls = ((start + n + 3) >> 2) - c0
     words = np.stack(stream_words(seed, STREAM_SAMPLE, np.arange(c0, c0 + ncalls, dtype=np.uint64), instance), axis=1)
     return words.reshape(-1)[(i - np.uint64(4 * c0)).astype(np.int64)]
+
+
+def replacement_words(seed: int, count: int, instance: int = 0):
+    """The uniform 32-bit word of each sample j in [0, count) of a draw with
+    replacement (stream 4)."""
+    ncalls = (count + 3) >> 2
+    words = np.stack(stream_words(seed, STREAM_REPLACE, np.arange(ncalls, dtype=np.uint64), instance), axis=1)
+    return words.reshape(-1)[:count]

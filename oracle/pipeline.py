@@ -11,6 +11,10 @@ Steps, in the paper's order:
 7. D_ii = 1/p_i with probability p_i;
 8. x_hat = argmin ||D A x - D b||_1 by linear programming.
 
+``sampling="replace"`` draws exactly s rows with replacement instead of step
+7 (the figure's caption); ``draws`` > 1 takes that many independent draws
+(and solves) from the one sampling pass.
+
 Test infrastructure only.
 """
 from __future__ import annotations
@@ -29,7 +33,7 @@ def form_x(A, b=None) -> np.ndarray:
 
 def l1_regress(A, b, s: int, r1: int, r2: int, s_out: float, seed: int,
                sign_flip: bool = True, lowp_pass2: bool = False, solve: bool = True,
-               pi2: str = "cauchy"):
+               pi2: str = "cauchy", sampling_mode: str = "bernoulli", draws: int = 1):
     """Run steps 1-8; return every intermediate in a dict.
 
     pi2 = "gaussian" runs the optimized regression figure instead: Pi2 of
@@ -49,11 +53,18 @@ def l1_regress(A, b, s: int, r1: int, r2: int, s_out: float, seed: int,
         lam = sampling.row_norm_estimates(X, M)
     total = float(lam.sum())
     p = sampling.probabilities(lam, s_out, total)
-    idx, w = sampling.select(p, seed)
-    out = dict(X=X, Y=Y, R=R, M=M, lam=lam, sum_lambda=total, p=p, idx=idx, w=w)
-    if solve:
-        A64 = np.asarray(A, dtype=np.float64)
-        b64 = np.asarray(b, dtype=np.float64)
-        x_hat, f_core = l1.lp(A64[idx], b64[idx], w)
-        out.update(x=x_hat, coreset_objective=f_core, objective=l1.objective(A64, b64, x_hat))
+    out = dict(X=X, Y=Y, R=R, M=M, lam=lam, sum_lambda=total, p=p, draws=[])
+    A64 = np.asarray(A, dtype=np.float64)
+    b64 = None if b is None else np.asarray(b, dtype=np.float64)
+    for k in range(draws):
+        if sampling_mode == "replace":
+            idx, w = sampling.select_with_replacement(lam, int(s_out), seed, k)
+        else:
+            idx, w = sampling.select(p, seed, k)
+        dr = dict(idx=idx, w=w)
+        if solve:
+            x_hat, f_core = l1.lp(A64[idx], b64[idx], w)
+            dr.update(x=x_hat, coreset_objective=f_core, objective=l1.objective(A64, b64, x_hat))
+        out["draws"].append(dr)
+    out.update(out["draws"][0])
     return out

@@ -7,6 +7,11 @@ FastCauchyRegression figure, steps 4-7:
 * D diagonal, D_ii = 1/p_i with probability p_i and 0 otherwise (step 7);
   the coreset is (D A, D b) restricted to the rows with D_ii != 0.
 
+The figure's caption allows instead exactly s rows drawn independently with
+replacement with probabilities p^_i = lambda_i / sum lambda
+(``select_with_replacement``); several independent draws from one sampling
+pass use instance numbers 0, 1, ... of the random streams.
+
 Readings: the median of an even count is the mean of the two middle order
 statistics; the paper's s is the expected coreset size s_out; row i is kept
 iff its uniform 32-bit word w_i < T_i = min(2^32, floor(p_i 2^32)), which is
@@ -59,3 +64,20 @@ def select(p, seed: int, instance: int = 0):
     keep = words < thresholds(p)
     idx = np.nonzero(keep)[0]
     return idx, 1.0 / p[idx]
+
+
+def select_with_replacement(lam, s: int, seed: int, instance: int = 0):
+    """Exactly s samples drawn independently with replacement with
+    probabilities p^_i = lambda_i / sum lambda (the caption of the
+    FastCauchyRegression figure), by inversion: sample j takes the row whose
+    interval [C_(i-1), C_i) of the running sums C of lambda contains u_j C_n,
+    u_j = (w_j + 1/2) / 2^32 with w_j its stream-4 word.  Returns the rows in
+    sample order (repeats included) and the weight 1 / (s p^_i) of each
+    sample, so that sum_j weight_j |r_(row_j)| estimates sum_i |r_i|."""
+    lam = np.asarray(lam, dtype=np.float64)
+    C = np.cumsum(lam)
+    total = C[-1]
+    u = (philox.replacement_words(seed, s, instance).astype(np.float64) + 0.5) * 2.0 ** -32
+    rows = np.searchsorted(C, u * total, side="right")
+    rows = np.minimum(rows, lam.shape[0] - 1)
+    return rows, total / (s * lam[rows])
