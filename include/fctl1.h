@@ -285,6 +285,51 @@ int l1_regress_batched(fct_ctx *ctx, const fct_instance *inst, int32_t count, fc
 int l1_select(fct_ctx *ctx, const float *lambda, const double *sum_lambda, int64_t n,
               int64_t s_out, uint64_t seed, int64_t cap, int64_t *idx, double *w, int64_t *S);
 
+/*
+ * Several coresets from one sampling pass (the large-scale evaluation of
+ * section "Empirical Evaluation" computes many approximate solutions in a
+ * single pass over the data), drawn in one of two ways:
+ *   FCT_SAMPLE_BERNOULLI: step 7 as l1_select, draw k keeping row i iff its
+ *     stream-3 word of instance k is below floor(p_i 2^32);
+ *   FCT_SAMPLE_REPLACE: exactly s_out rows drawn independently with
+ *     replacement with probabilities lambda_i / sum lambda (the caption of
+ *     the regression figure): sample j of draw k takes the row i whose
+ *     interval [C_(i-1), C_i) of the running sums of lambda holds u C_n,
+ *     u = (w + 1/2) / 2^32 with w its stream-4 word of instance k, and weight
+ *     C_n / (s_out lambda_i).  The running sums are FP64 over 256-row blocks
+ *     and their prefix; a target within rounding of a block's end takes the
+ *     block's last row with lambda > 0.
+ */
+enum { FCT_SAMPLE_BERNOULLI = 0, FCT_SAMPLE_REPLACE = 1 };
+
+/*
+ * l1_select_draw: draw `draw` (>= 0) of either kind from row-norm estimates
+ * already computed (l1_sample_probs).
+ *   lambda: device FP32 [n]; sum_lambda: device FP64 scalar (Bernoulli only;
+ *     the draw with replacement forms its own running sums).
+ *   idx: device int64 [cap]; w: device FP64 [cap]: Bernoulli: the kept rows
+ *     ascending and 1/p_i; with replacement: the s_out samples in sample
+ *     order (a row drawn twice appears twice) and their weights (cap >= s_out).
+ *   S: host, the count; FCT_ERR_CAPACITY when S > cap (first cap written).
+ */
+int l1_select_draw(fct_ctx *ctx, const float *lambda, const double *sum_lambda, int64_t n,
+                   int64_t s_out, uint64_t seed, int32_t draw, int32_t mode, int64_t cap,
+                   int64_t *idx, double *w, int64_t *S);
+
+/*
+ * l1_regress_multi: the regression figure's steps 1-5 once (one sketch, one
+ * pass over X for lambda), then K draws (k = 0 .. K-1) of step 6-7 of the
+ * given kind, each gathered into its own coreset, and the K coreset solves
+ * of step 8 in one launch (one workgroup per draw).  Arguments as l1_regress
+ * (FP32 or FP64 data, d <= 64, eps sets s_out when prm->s_out <= 0).
+ * Outputs (host): x[k d .. k d + d), obj[k] (may be NULL), S[k] (may be
+ * NULL), status[k] as l1_regress_batched's.
+ * Returns FCT_OK if every draw succeeded, else the first failing status.
+ */
+int l1_regress_multi(fct_ctx *ctx, const void *A, const void *b, int64_t n, int32_t d, int64_t lda,
+                     fct_dtype dt, double eps, const fct_params *prm, int32_t K, int32_t mode,
+                     double *x, double *obj, int64_t *S, int32_t *status);
+
 /* ---- supporting calls (diagnostics and data preparation) ---------------- */
 
 /*
@@ -311,7 +356,7 @@ int fct_lowp_residual(fct_ctx *ctx, const void *A, const void *b, int64_t n, int
                       double *R_res);
 
 /* words: device uint32 [4 * count], the Philox4x32-10 words of calls
- * idx0 .. idx0 + count - 1 of `stream` (0..3) under `seed`, instance 0. */
+ * idx0 .. idx0 + count - 1 of `stream` (0..4) under `seed`, instance 0. */
 int fct_rng_words(fct_ctx *ctx, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                   uint32_t *words);
 

@@ -13,14 +13,23 @@
 //   stream 1: idx = j >> 7, bit j & 31 of word (j >> 5) & 3 -> sign D(j);
 //   stream 2: idx = a * r2 + c, word 0 -> Cauchy Pi2[a][c] (words 0 and 1 ->
 //             Gaussian Pi2[a][c] for the optimized regression);
-//   stream 3: idx = i >> 2, word i & 3 -> uniform deciding row i.
+//   stream 3: idx = i >> 2, word i & 3 -> uniform deciding row i (instance
+//             k: the k-th of several draws from one sampling pass);
+//   stream 4: idx = j >> 2, word j & 3 -> uniform of sample j of a draw with
+//             replacement (instance k: the k-th draw).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace fctl1 {
 
-enum : uint32_t { kStreamPi1 = 0, kStreamSign = 1, kStreamPi2 = 2, kStreamSample = 3 };
+enum : uint32_t {
+  kStreamPi1 = 0,
+  kStreamSign = 1,
+  kStreamPi2 = 2,
+  kStreamSample = 3,
+  kStreamReplace = 4
+};
 
 // a ^ b ^ c in one v_bitop3_b32 (truth table 0x96: odd parity of the inputs)
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {

@@ -137,6 +137,15 @@ struct SelectArgs {
 };
 int select_grid(int64_t n);
 hipError_t launch_select(const SelectArgs& a, hipStream_t st);
+// Sampling with replacement: block sums bs [rep_blocks(n)], their prefix pre
+// [rep_blocks(n)], chunk sums cs and offsets co [rep_chunks(n)] and the total
+// tot [1] (built when build_cdf), then s samples of draw `instance`.
+int64_t rep_blocks(int64_t n);
+int64_t rep_chunks(int64_t n);
+hipError_t launch_select_replace(const float* lambda, int64_t n, int64_t s, uint64_t seed,
+                                 uint32_t instance, double* bs, double* pre, double* cs,
+                                 double* co, double* tot, bool build_cdf, int64_t* idx, double* w,
+                                 int64_t* S, hipStream_t st);
 hipError_t launch_probs_only(const SelectArgs& a, hipStream_t st);
 
 // Gather the kept rows of A and b (unscaled) into column-major outputs.

@@ -424,7 +424,8 @@ void carve_probs(C& cv, const fct_ctx* c, int q, int r2, int64_t n, int kind) {
 }
 
 int run_select(fct_ctx* c, Carve& cv, const float* lambda, const double* sum_lambda, int64_t n,
-               double s_out, uint64_t seed, int64_t cap, int64_t* idx, double* w, int64_t* S_dev) {
+               double s_out, uint64_t seed, int64_t cap, int64_t* idx, double* w, int64_t* S_dev,
+               uint32_t instance = 0) {
   const int nb = select_grid(n);
   SelectArgs a{};
   a.lambda = lambda;
@@ -432,7 +433,7 @@ int run_select(fct_ctx* c, Carve& cv, const float* lambda, const double* sum_lam
   a.n = n;
   a.s_out = s_out;
   a.seed = seed;
-  a.instance = 0;
+  a.instance = instance;
   a.p_out = nullptr;
   a.lookback = cv.take<uint64_t>((size_t)nb + 1);
   a.fail = c->flags + 1;
@@ -448,6 +449,28 @@ template <typename C>
 void carve_select(C& cv, int64_t n) {
   const int nb = select_grid(n);
   cv.template take<uint64_t>((size_t)nb + 1);
+}
+
+// The running-sum table of sampling with replacement.
+struct RepCdf {
+  double *bs, *pre, *cs, *co, *tot;
+};
+template <typename C>
+void carve_rep(C& cv, int64_t n) {
+  cv.template take<double>((size_t)rep_blocks(n));
+  cv.template take<double>((size_t)rep_blocks(n));
+  cv.template take<double>((size_t)rep_chunks(n));
+  cv.template take<double>((size_t)rep_chunks(n));
+  cv.template take<double>(1);
+}
+RepCdf take_rep(Carve& cv, int64_t n) {
+  RepCdf r;
+  r.bs = cv.take<double>((size_t)rep_blocks(n));
+  r.pre = cv.take<double>((size_t)rep_blocks(n));
+  r.cs = cv.take<double>((size_t)rep_chunks(n));
+  r.co = cv.take<double>((size_t)rep_chunks(n));
+  r.tot = cv.take<double>(1);
+  return r;
 }
 
 }  // namespace
@@ -846,6 +869,38 @@ int l1_select(fct_ctx* c, const float* lambda, const double* sum_lambda, int64_t
   return *S > cap ? FCT_ERR_CAPACITY : FCT_OK;
 }
 
+int l1_select_draw(fct_ctx* c, const float* lambda, const double* sum_lambda, int64_t n,
+                   int64_t s_out, uint64_t seed, int32_t draw, int32_t mode, int64_t cap,
+                   int64_t* idx, double* w, int64_t* S) {
+  if (!c || !lambda || n < 1 || s_out < 1 || cap < 1 || !idx || !w || !S || draw < 0)
+    return FCT_ERR_BAD_ARG;
+  if (mode == FCT_SAMPLE_BERNOULLI && !sum_lambda) return FCT_ERR_BAD_ARG;
+  if (mode != FCT_SAMPLE_BERNOULLI && mode != FCT_SAMPLE_REPLACE) return FCT_ERR_BAD_ARG;
+  if (mode == FCT_SAMPLE_REPLACE && cap < s_out) return FCT_ERR_BAD_ARG;
+  Measure m;
+  m.take<int64_t>(1);
+  if (mode == FCT_SAMPLE_BERNOULLI) carve_select(m, n);
+  else carve_rep(m, n);
+  int st;
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  int64_t* S_dev = cv.take<int64_t>(1);
+  if (mode == FCT_SAMPLE_BERNOULLI) {
+    if ((st = run_select(c, cv, lambda, sum_lambda, n, (double)s_out, seed, cap, idx, w, S_dev,
+                         (uint32_t)draw)))
+      return st;
+  } else {
+    const RepCdf r = take_rep(cv, n);
+    HIP_TRY(launch_select_replace(lambda, n, s_out, seed, (uint32_t)draw, r.bs, r.pre, r.cs, r.co,
+                                  r.tot, true, idx, w, S_dev, c->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(c->pinned, S_dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  const int fl = read_flags(c);
+  std::memcpy(S, c->pinned, sizeof(int64_t));
+  if (fl) return fl;
+  return *S > cap ? FCT_ERR_CAPACITY : FCT_OK;
+}
+
 int l1_solve(fct_ctx* c, const void* At, const void* bt, const double* w, int64_t S, int32_t d,
              int64_t ldat, fct_dtype dt, int32_t iters, double* x, double* obj) {
   if (!c || !At || !bt || !w || S < 1 || d < 1 || d > 64 || ldat < S || !x) return FCT_ERR_BAD_ARG;
@@ -1210,9 +1265,157 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
   return first;
 }
 
+int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
+                     fct_dtype dt, double eps, const fct_params* prm_in, int32_t K, int32_t mode,
+                     double* x, double* obj, int64_t* S, int32_t* status) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!b || !x || !status || !prm_in || K < 1 || d > 64 || (dt != FCT_F32 && dt != FCT_F64))
+    return FCT_ERR_BAD_ARG;
+  if (mode != FCT_SAMPLE_BERNOULLI && mode != FCT_SAMPLE_REPLACE) return FCT_ERR_BAD_ARG;
+  fct_params prm = *prm_in;
+  if (prm.s_out <= 0) {
+    if (!(eps > 0.0)) return FCT_ERR_BAD_ARG;
+    prm.s_out = (int64_t)std::ceil(20.0 * (d + 1) / eps);
+  }
+  if ((st = check_params(&prm, d + 1))) return st;
+  const int iters = prm.irls_iters > 0 ? prm.irls_iters : 80;
+  const int q = d + 1;
+  int64_t cap;
+  if (mode == FCT_SAMPLE_REPLACE) {
+    cap = prm.s_out;
+  } else {
+    cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
+    if (cap > n) cap = n;
+  }
+  const size_t es = esize(dt);
+  const int64_t n_pad = (n + prm.s - 1) / prm.s * prm.s;
+  int perr = 0;
+  const Pass1Plan plan = make_pass1_plan(c, n_pad, q, prm.s, prm.r1, es, prm.flags, &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  // one sampling pass: R, lambda, sum lambda; then K draws, each with its
+  // coreset, and the solver's arguments, outputs and work
+  auto layout = [&](auto& cv) {
+    cv.template take<double>((size_t)q * q);
+    cv.template take<float>((size_t)n);
+    cv.template take<double>(1);
+    cv.template take<int64_t>((size_t)K);
+    cv.template take<char>((size_t)K * sizeof(IrlsArgs));
+    cv.template take<double>((size_t)K * 72);
+    for (int k = 0; k < K; ++k) {
+      cv.template take<char>((size_t)cap * d * es);
+      cv.template take<char>((size_t)cap * es);
+      cv.template take<double>((size_t)cap);
+      cv.template take<int64_t>((size_t)cap);
+      cv.template take<double>(irls_batched_work_doubles(d));
+      cv.template take<double>(72);
+      cv.template take<int>(4);
+    }
+    if (mode == FCT_SAMPLE_REPLACE) carve_rep(cv, n);
+  };
+  Measure m;
+  layout(m);
+  const size_t fixed = m.off;
+  Measure ma, mb, mc;
+  carve_sketch(ma, plan, n_pad, q, prm.r1, es, true);
+  carve_probs(mb, c, q, prm.r2, n, dt == FCT_F64 ? kPass2F64 : kPass2F32);
+  carve_select(mc, n);
+  const size_t rest = std::max(ma.off, std::max(mb.off, mc.off)) + 1024;
+  if ((st = ensure_scratch(c, fixed + rest + 256))) return st;
+  const size_t pin = std::max((size_t)K * sizeof(IrlsArgs), (size_t)K * 72 * sizeof(double));
+  if ((st = batch_ensure_aux(c, pin))) return st;
+  Carve cv(c->scratch);
+  double* R = cv.take<double>((size_t)q * q);
+  float* lam = cv.take<float>((size_t)n);
+  double* sl = cv.take<double>(1);
+  int64_t* S_dev = cv.take<int64_t>((size_t)K);
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>((size_t)K * sizeof(IrlsArgs)));
+  double* out_dev = cv.take<double>((size_t)K * 72);
+  std::vector<IrlsArgs> args((size_t)K);
+  std::vector<int64_t*> idx((size_t)K);
+  for (int k = 0; k < K; ++k) {
+    IrlsArgs& a = args[k];
+    a.At = cv.take<char>((size_t)cap * d * es);
+    a.bt = cv.take<char>((size_t)cap * es);
+    a.w = cv.take<double>((size_t)cap);
+    idx[k] = cv.take<int64_t>((size_t)cap);
+    double* work = cv.take<double>(irls_batched_work_doubles(d));
+    double* outv = cv.take<double>(72);
+    a.status = cv.take<int>(4);
+    a.S_dev = S_dev + k;
+    a.cap = cap;
+    a.ldat = cap;
+    a.d = d;
+    a.iters = iters;
+    a.row_target = 1 << 30;
+    a.part = work;
+    a.bar = irls_batched_bar(work, d);
+    a.x_out = outv;
+    a.obj_out = outv + 64;
+  }
+  RepCdf rep{};
+  if (mode == FCT_SAMPLE_REPLACE) rep = take_rep(cv, n);
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_sketch(c, sub, A, n, d, lda, dt, b, prm.s, prm.r1, prm.seed, prm.flags, nullptr,
+                         R, nullptr, plan)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_probs(c, sub, A, b, n, d, lda, dt, R, prm.r2, prm.seed, lam, sl, prm.flags)))
+      return st;
+  }
+  for (int k = 0; k < K; ++k) {
+    double* w = const_cast<double*>(args[k].w);
+    if (mode == FCT_SAMPLE_REPLACE) {
+      HIP_TRY(launch_select_replace(lam, n, prm.s_out, prm.seed, (uint32_t)k, rep.bs, rep.pre,
+                                    rep.cs, rep.co, rep.tot, k == 0, idx[k], w, S_dev + k,
+                                    c->stream));
+    } else {
+      Carve sub(cv.base);
+      sub.off = cv.off;
+      if ((st = run_select(c, sub, lam, sl, n, (double)prm.s_out, prm.seed, cap, idx[k], w,
+                           S_dev + k, (uint32_t)k)))
+        return st;
+    }
+    HIP_TRY(launch_gather(A, b, lda, d, idx[k], S_dev + k, cap, const_cast<void*>(args[k].At),
+                          const_cast<void*>(args[k].bt), cap, dt == FCT_F64, c->stream));
+  }
+  std::memcpy(c->bpinned, args.data(), (size_t)K * sizeof(IrlsArgs));
+  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)K * sizeof(IrlsArgs), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the pinned block is reused for the outputs
+  prof_begin(c, 2);
+  HIP_TRY(launch_irls_batched(args_dev, K, dt == FCT_F64, c->stream));
+  prof_end(c, 2);
+  hipLaunchKernelGGL(batch_collect_kernel, dim3(K), dim3(64), 0, c->stream, args_dev, K, out_dev);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->bpinned, out_dev, (size_t)K * 72 * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  const int fl = read_flags(c);
+  const double* h = reinterpret_cast<const double*>(c->bpinned);
+  int first = FCT_OK;
+  for (int k = 0; k < K; ++k) {
+    const double* row = h + (size_t)k * 72;
+    const int64_t Sk = (int64_t)row[65];
+    int stk = (int)row[66];
+    if (Sk > cap) stk = FCT_ERR_CAPACITY;
+    status[k] = stk;
+    for (int i = 0; i < d; ++i) x[(size_t)k * d + i] = row[i];
+    if (obj) obj[k] = row[64];
+    if (S) S[k] = Sk;
+    if (stk != FCT_OK && first == FCT_OK) first = stk;
+  }
+  if (fl) return fl;
+  return first;
+}
+
 int fct_rng_words(fct_ctx* c, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                   uint32_t* words) {
-  if (!c || !words || count < 0 || stream > 3) return FCT_ERR_BAD_ARG;
+  if (!c || !words || count < 0 || stream > 4) return FCT_ERR_BAD_ARG;
   if (count == 0) return FCT_OK;
   HIP_TRY(launch_rng_words(stream, seed, idx0, count, words, c->stream));
   return FCT_OK;

@@ -218,6 +218,178 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---- sampling with replacement ---------------------------------------------
+//
+// Exactly s samples, independent, with probabilities lambda_i / sum lambda
+// (the caption of the regression figure), by inversion of the running sums
+// C of lambda: sample j takes the row i with C_(i-1) <= u_j C_n < C_i, u_j =
+// (w_j + 1/2) / 2^32 from its stream-4 word.  C is held at the granularity of
+// 256-row blocks (FP64 sums of 256 rows, their exclusive prefix in fixed-size
+// chunks); a sample finds its block by binary search and its row by running
+// the block's sum in row order.
+
+static constexpr int kRepBlock = 256;   // rows per block sum
+static constexpr int kRepChunk = 1024;  // block sums per scan chunk
+
+int64_t rep_blocks(int64_t n) { return (n + kRepBlock - 1) / kRepBlock; }
+int64_t rep_chunks(int64_t n) { return (rep_blocks(n) + kRepChunk - 1) / kRepChunk; }
+
+// bs[b]: a wave per block, each lane its 4 consecutive rows in order, the
+// lanes' sums by a fixed tree
+__global__ void __launch_bounds__(256) rep_block_sums_kernel(const float* __restrict__ lam, int64_t n,
+                                                             int64_t nb, double* __restrict__ bs) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); blk < nb;
+       blk += (int64_t)gridDim.x * 4) {
+    const int64_t r = blk * kRepBlock + 4 * lane;
+    double v = 0.0;
+    if (r + 3 < n) {
+      const float4 x = *reinterpret_cast<const float4*>(lam + r);
+      v = (((double)x.x + (double)x.y) + (double)x.z) + (double)x.w;
+    } else {
+      for (int k = 0; k < 4; ++k)
+        if (r + k < n) v += (double)lam[r + k];
+    }
+    v = wave_sum_dpp(v);
+    if (lane == 0) bs[blk] = v;
+  }
+}
+
+// cs[c]: the sum of bs over chunk c (each thread 4 in order, then a fixed tree)
+__global__ void __launch_bounds__(256) rep_chunk_sums_kernel(const double* __restrict__ bs, int64_t nb,
+                                                             double* __restrict__ cs) {
+  __shared__ double red[4];
+  const int64_t b0 = (int64_t)blockIdx.x * kRepChunk + 4 * threadIdx.x;
+  double v = 0.0;
+  for (int k = 0; k < 4; ++k)
+    if (b0 + k < nb) v += bs[b0 + k];
+  v = wave_sum_dpp(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) cs[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// one workgroup: co = exclusive prefix of cs (runs per thread in order, then
+// the run totals in order); tot = the sum of everything
+__global__ void __launch_bounds__(1024) rep_chunk_scan_kernel(const double* __restrict__ cs, int nc,
+                                                              double* __restrict__ co,
+                                                              double* __restrict__ tot) {
+  __shared__ double run[1024];
+  const int T = blockDim.x;
+  const int per = (nc + T - 1) / T;
+  const int lo = threadIdx.x * per, hi = min(nc, lo + per);
+  double s = 0.0;
+  for (int i = lo; i < hi; ++i) s += cs[i];
+  run[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int t = 0; t < T; ++t) {
+      const double v = run[t];
+      run[t] = acc;
+      acc += v;
+    }
+    *tot = acc;
+  }
+  __syncthreads();
+  double o = run[threadIdx.x];
+  for (int i = lo; i < hi; ++i) {
+    co[i] = o;
+    o += cs[i];
+  }
+}
+
+// pre[b] = co[chunk] + the exclusive prefix of bs within the chunk (each
+// thread 4 in order, the thread totals scanned in thread order)
+__global__ void __launch_bounds__(256) rep_block_prefix_kernel(const double* __restrict__ bs, int64_t nb,
+                                                               const double* __restrict__ co,
+                                                               double* __restrict__ pre) {
+  __shared__ double ts[256];
+  const int64_t b0 = (int64_t)blockIdx.x * kRepChunk + 4 * threadIdx.x;
+  double v[4], s = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    v[k] = b0 + k < nb ? bs[b0 + k] : 0.0;
+    s += v[k];
+  }
+  ts[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = co[blockIdx.x];
+    for (int t = 0; t < 256; ++t) {
+      const double x = ts[t];
+      ts[t] = acc;
+      acc += x;
+    }
+  }
+  __syncthreads();
+  double o = ts[threadIdx.x];
+  for (int k = 0; k < 4; ++k)
+    if (b0 + k < nb) {
+      pre[b0 + k] = o;
+      o += v[k];
+    }
+}
+
+// one thread per sample: its block by binary search over pre (the last block
+// whose prefix is <= the target: empty blocks are skipped), its row by the
+// block's running sum; a target past the block's last running sum (the two
+// sums rounded in another order) takes the block's last row with lambda > 0
+__global__ void __launch_bounds__(256) rep_sample_kernel(const float* __restrict__ lam, int64_t n,
+                                                         const double* __restrict__ pre, int64_t nb,
+                                                         const double* __restrict__ tot, int64_t s,
+                                                         uint64_t seed, uint32_t instance,
+                                                         int64_t* __restrict__ idx,
+                                                         double* __restrict__ w,
+                                                         int64_t* __restrict__ S) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) *S = s;
+  if (j >= s) return;
+  const uint4 wv = stream_words(seed, kStreamReplace, (uint64_t)j >> 2, instance);
+  const uint32_t sel = (uint32_t)j & 3u;
+  const uint32_t word = sel == 0 ? wv.x : sel == 1 ? wv.y : sel == 2 ? wv.z : wv.w;
+  const double total = *tot;
+  const double t = ((double)word + 0.5) * 0x1p-32 * total;
+  int64_t lo = 0, hi = nb - 1;  // pre[0] = 0 <= t
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t r0 = lo * kRepBlock, r1 = min(n, r0 + kRepBlock);
+  double c = pre[lo];
+  int64_t row = -1, last = r0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const float v = lam[r];
+    if (v > 0.0f) last = r;
+    c += (double)v;
+    if (t < c) {
+      row = r;
+      break;
+    }
+  }
+  if (row < 0) row = last;
+  idx[j] = row;
+  w[j] = total / ((double)s * (double)lam[row]);
+}
+
+hipError_t launch_select_replace(const float* lambda, int64_t n, int64_t s, uint64_t seed,
+                                 uint32_t instance, double* bs, double* pre, double* cs,
+                                 double* co, double* tot, bool build_cdf, int64_t* idx, double* w,
+                                 int64_t* S, hipStream_t st) {
+  const int64_t nb = rep_blocks(n), nc = rep_chunks(n);
+  if (build_cdf) {
+    int64_t g = (nb + 3) / 4;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(rep_block_sums_kernel, dim3((unsigned)g), dim3(256), 0, st, lambda, n, nb, bs);
+    hipLaunchKernelGGL(rep_chunk_sums_kernel, dim3((unsigned)nc), dim3(256), 0, st, bs, nb, cs);
+    hipLaunchKernelGGL(rep_chunk_scan_kernel, dim3(1), dim3(1024), 0, st, cs, (int)nc, co, tot);
+    hipLaunchKernelGGL(rep_block_prefix_kernel, dim3((unsigned)nc), dim3(256), 0, st, bs, nb, co, pre);
+  }
+  hipLaunchKernelGGL(rep_sample_kernel, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, st, lambda,
+                     n, pre, nb, tot, s, seed, instance, idx, w, S);
+  return hipGetLastError();
+}
+
 // probabilities only (l1_sample_probs with p requested)
 __global__ void __launch_bounds__(256) probs_kernel(SelectArgs a) {
   const double total = *a.sum_lambda;

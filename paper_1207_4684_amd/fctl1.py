@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfctl1.so")
 
 FCT_F32, FCT_F64, FCT_BF16 = 0, 1, 2
+FCT_SAMPLE_BERNOULLI, FCT_SAMPLE_REPLACE = 0, 1
 FCT_FLAG_NO_SIGN_FLIP = 1
 FCT_FLAG_DETERMINISTIC = 2
 FCT_FLAG_GAUSSIAN_PI2 = 4
@@ -80,6 +81,10 @@ def _load():
         "fct_fwht": (ctypes.c_int, [P, P, I64, I32]),
         "fct_to_bf16": (ctypes.c_int, [P, P, I64, P]),
         "fct_lowp_residual": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, P]),
+        "l1_select_draw": (ctypes.c_int, [P, P, P, I64, I64, U64, I32, I32, I64, P, P, PI64]),
+        "l1_regress_multi": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, D,
+                                            ctypes.POINTER(fct_params), I32, I32, PD, PD, PI64,
+                                            ctypes.POINTER(ctypes.c_int32)]),
         "fct_l1_objective": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, PD, PD]),
         "l1_solve": (ctypes.c_int, [P, P, P, P, I64, I32, I64, ctypes.c_int, I32, PD, PD]),
         "l1_select": (ctypes.c_int, [P, P, P, I64, I64, U64, I64, P, P, PI64]),
@@ -102,7 +107,8 @@ EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream
             "fct_sketch_window", "l1_sample_probs", "l1_sample_probs_ex", "l1_sample_probs_noalloc",
             "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams", "fct_fwht",
             "fct_to_bf16", "fct_lowp_residual", "fct_l1_objective", "l1_solve", "l1_select",
-            "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option")
+            "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option",
+            "l1_select_draw", "l1_regress_multi")
 
 
 def _check(st: int, where: str):
@@ -344,6 +350,34 @@ def l1_regress_batched(ctx, items, eps=0.05):
         out.append(dict(x=list(x[off:off + d]), obj=obj[i], S=S[i], s=s_used[i], status=status[i]))
         off += d
     return out, st
+
+
+def l1_select_draw(ctx, lam, sum_lambda, s_out, seed, draw, mode, cap):
+    """idx, w and S of draw ``draw`` (Bernoulli or with replacement)."""
+    n = lam.numel()
+    idx = torch.empty(cap, dtype=torch.int64, device=lam.device)
+    w = torch.empty(cap, dtype=torch.float64, device=lam.device)
+    S = ctypes.c_int64()
+    _check(ctx.call(_lib.l1_select_draw, ctx.handle, _ptr(lam), _ptr(sum_lambda), n, int(s_out),
+                    seed, int(draw), int(mode), int(cap), _ptr(idx), _ptr(w), ctypes.byref(S)),
+           "l1_select_draw")
+    return idx, w, S.value
+
+
+def l1_regress_multi(ctx, A, b, prm, K, mode=FCT_SAMPLE_BERNOULLI, eps=0.05):
+    """K draws from one sampling pass and their K solves: (x (K, d) numpy,
+    obj, S, status, return status)."""
+    import numpy as np
+    n, d, lda = _cm(A)
+    x = (ctypes.c_double * (K * d))()
+    obj = (ctypes.c_double * K)()
+    S = (ctypes.c_int64 * K)()
+    status = (ctypes.c_int32 * K)()
+    st = ctx.call(_lib.l1_regress_multi, ctx.handle, _ptr(A), _ptr(b), n, d, lda, _dt(A), eps,
+                  ctypes.byref(prm), int(K), int(mode), x, obj, S, status)
+    if st not in (0, -4, -6, -5) or (st != 0 and all(v == 0 for v in status)):
+        _check(st, "l1_regress_multi")
+    return (np.array(x[:]).reshape(K, d), list(obj), list(S), list(status), st)
 
 
 def l1_solve(ctx, At, bt, w, iters=0):
