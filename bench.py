@@ -230,7 +230,8 @@ def jaccard(a, b):
     return len(a & b) / max(1, len(a | b))
 
 
-def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, err_report=False):
+def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, err_report=False,
+                 multi=0):
     """Time l1_regress on workload w (plain and, for FP32 data, the BF16
     sampling pass); pass times from the library's events; objectives from the
     library (fct_l1_objective) against an all-rows solve by the library."""
@@ -312,6 +313,23 @@ def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, er
         if err_report:
             rec["bf16_error"] = bf16_error_report(F, torch, ctx, w, Ad, bd, Al, bl)
         del Al, bl
+    xs_multi = {}
+    if multi > 0 and not f64:
+        # K coresets (and solves) from one sampling pass, both kinds of draw
+        m = {"K": multi, "single_plain_ms": rec["plain_ms"]}
+        for name, mode in (("bernoulli", F.FCT_SAMPLE_BERNOULLI), ("replace", F.FCT_SAMPLE_REPLACE)):
+            def mstep():
+                return F.l1_regress_multi(ctx, Ad, bd, prm, multi, mode, eps=w.eps)
+            t_m, out_m = timed_steps(torch, mstep, 3, 1, flush)
+            tm = statistics.median(t_m)
+            xs_multi[name] = out_m[0]
+            m[f"{name}_ms"] = round(tm * 1e3, 4)
+            m[f"{name}_solutions_per_s"] = round(multi / tm, 1)
+            m[f"{name}_speedup_vs_single_calls"] = round(multi * med / tm, 3)
+            m[f"{name}_coreset_rows"] = [int(v) for v in out_m[2]]
+        rec["multi"] = m
+        progress(f"{w.name}: {multi} draws per pass: bernoulli {m['bernoulli_ms']} ms, "
+                 f"replace {m['replace_ms']} ms")
     if ref:
         x_ref, _ = F.l1_solve(ctx, Ad, bd, torch.ones(w.n, dtype=torch.float64, device="cuda"),
                               iters=120)
@@ -320,6 +338,9 @@ def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, er
         rec["ratio_plain"] = f_plain / f_ref
         if "objective_bf16" in rec:
             rec["ratio_bf16"] = rec["objective_bf16"] / f_ref
+        for name, X in xs_multi.items():
+            rec["multi"][f"{name}_ratio_max"] = max(
+                F.fct_l1_objective(ctx, Ad, bd, X[k]) / f_ref for k in range(X.shape[0]))
     del Ad, bd
     torch.cuda.empty_cache()
     return rec
@@ -449,6 +470,8 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256, help="instances of the batching workload (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--multi", type=int, default=16,
+                    help="coresets per sampling pass timed on the headline workload (0 = skip)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 26, help="rows of the CPU baseline's sample")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solves")
@@ -471,7 +494,7 @@ def main():
     ctx = F.Context(0)
     flush = Flusher(torch)
     head = run_workload(F, torch, ctx, w, args.steps, args.warmup, flush, ref=not args.skip_ref,
-                        err_report=w.dtype == "f32")
+                        err_report=w.dtype == "f32", multi=args.multi)
     if args.profile_copy_mib > 0:
         src = torch.empty(args.profile_copy_mib << 18, dtype=torch.float32, device="cuda")
         src.fill_(1.0)
