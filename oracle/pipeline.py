@@ -68,3 +68,53 @@ def l1_regress(A, b, s: int, r1: int, r2: int, s_out: float, seed: int,
         out["draws"].append(dr)
     out.update(out["draws"][0])
     return out
+
+
+def l1_regress_mrhs(A, B, s: int, r1: int, r2: int, s_out: float, seed: int,
+                    sign_flip: bool = True):
+    """Multiple l1 regression (section "Generalizing to Multiple l1
+    Regression"): X = [A, -B], the figure's steps 1-7 with q = d + k columns,
+    then min_w ||D (A w - B_j)||_1 for every column j of B by LP."""
+    A64 = np.asarray(A, dtype=np.float64)
+    B64 = np.asarray(B, dtype=np.float64)
+    X = np.hstack([A64, -B64])
+    Y = fct.pi1_apply(X, s, r1, seed, sign_flip=sign_flip)
+    R = basis.qr_r(Y)
+    M = basis.m_matrix(R, seed, r2)
+    lam = sampling.row_norm_estimates(X, M)
+    total = float(lam.sum())
+    p = sampling.probabilities(lam, s_out, total)
+    idx, w = sampling.select(p, seed)
+    k = B64.shape[1]
+    W = np.zeros((A64.shape[1], k))
+    f = np.zeros(k)
+    for j in range(k):
+        W[:, j], _ = l1.lp(A64[idx], B64[idx, j], w)
+        f[j] = l1.objective(A64, B64[:, j], W[:, j])
+    return dict(X=X, R=R, M=M, lam=lam, sum_lambda=total, p=p, idx=idx, w=w, W=W, objective=f)
+
+
+def l1_subspace(A, s: int, r1: int, r2: int, s_out: float, seed: int, sign_flip: bool = True):
+    """l1-norm subspace approximation (section "Application to l1 norm
+    Subspace Approximation"): one coreset of X = A (the figure with b empty),
+    then for every column j the constrained regression min_{w: w_j = -1}
+    ||D A w||_1 by LP, err_j = ||A w_j||_1 on all rows, and j* = argmin."""
+    A64 = np.asarray(A, dtype=np.float64)
+    n, d = A64.shape
+    Y = fct.pi1_apply(A64, s, r1, seed, sign_flip=sign_flip)
+    R = basis.qr_r(Y)
+    M = basis.m_matrix(R, seed, r2)
+    lam = sampling.row_norm_estimates(A64, M)
+    total = float(lam.sum())
+    p = sampling.probabilities(lam, s_out, total)
+    idx, wt = sampling.select(p, seed)
+    W = np.zeros((d, d))
+    err = np.zeros(d)
+    for j in range(d):
+        others = [c for c in range(d) if c != j]
+        v, _ = l1.lp(A64[idx][:, others], A64[idx, j], wt)
+        W[others, j] = v
+        W[j, j] = -1.0
+        err[j] = float(np.abs(A64 @ W[:, j]).sum())
+    return dict(R=R, M=M, lam=lam, sum_lambda=total, p=p, idx=idx, w=wt, W=W, err=err,
+                j_star=int(np.argmin(err)))
