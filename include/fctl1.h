@@ -330,6 +330,47 @@ int l1_regress_multi(fct_ctx *ctx, const void *A, const void *b, int64_t n, int3
                      fct_dtype dt, double eps, const fct_params *prm, int32_t K, int32_t mode,
                      double *x, double *obj, int64_t *S, int32_t *status);
 
+/*
+ * l1_regress_mrhs: multiple l1 regression (section "Generalizing to Multiple
+ * l1 Regression", Theorem FCRmult): min_W ||A W - B||_1 for B with k columns.
+ * X = [A, -B] (q = d + k columns) is sketched and sampled once, as in the
+ * regression figure with q in place of d + 1, and the k weighted regressions
+ * min_w ||D (A w - B_j)||_1 are solved on the one coreset in one launch (one
+ * workgroup per column).
+ *   A: device, column-major n x d (lda >= n); B: device, column-major n x k
+ *     (ldb >= n), same element type dt (F32 or F64); d <= 64, d + k <= 88.
+ *   eps: s_out = ceil(20 q / eps) when prm->s_out <= 0.
+ *   W: host FP64 d x k, column-major (column j solves right-hand side j);
+ *   obj: host k or NULL, coreset objectives; S: host or NULL, coreset size;
+ *   status: host k, as l1_regress_batched's.
+ *   R_out, lambda_out: device or NULL: R of the sketch ((d + k) x (d + k),
+ *     column-major, FP64) and the row-norm estimates (n, FP32).
+ */
+int l1_regress_mrhs(fct_ctx *ctx, const void *A, const void *B, int64_t n, int32_t d, int32_t k,
+                    int64_t lda, int64_t ldb, fct_dtype dt, double eps, const fct_params *prm,
+                    double *W, double *obj, int64_t *S, int32_t *status, double *R_out,
+                    float *lambda_out);
+
+/*
+ * l1_subspace: l1-norm subspace approximation (section "Application to l1
+ * norm Subspace Approximation", Theorem L1Sub): the best (d - 1)-dimensional
+ * subspace for the n points (rows of A) by d constrained regressions
+ * min_{w: w_j = -1} ||A w||_1, one coreset of X = A for all of them (the
+ * regression figure with b empty), the d solves in one launch, then
+ * err_j = ||A w_j||_1 over all rows and j* = argmin_j err_j.  The points
+ * projected onto the answer are A with column j* replaced by A w (w = w_j*
+ * with its -1 entry set to 0).
+ *   A: device, column-major n x d, 2 <= d <= 64, F32 or F64.
+ *   W: host FP64 d x d, column-major: column j is w_j (W_jj = -1).
+ *   err: host d, FP64; j_star: host; S: host or NULL, coreset size;
+ *   status: host d, per regression.
+ *   R_out, lambda_out: device or NULL: R of the sketch of A (d x d) and the
+ *     row-norm estimates (n, FP32).
+ */
+int l1_subspace(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda, fct_dtype dt,
+                double eps, const fct_params *prm, double *W, double *err, int32_t *j_star,
+                int64_t *S, int32_t *status, double *R_out, float *lambda_out);
+
 /* ---- supporting calls (diagnostics and data preparation) ---------------- */
 
 /*
@@ -405,6 +446,11 @@ int fct_set_option(fct_ctx *ctx, int option, int64_t value);
 
 /* BF16 copy (round to nearest even) of a device FP32 array. */
 int fct_to_bf16(fct_ctx *ctx, const float *x, int64_t count, uint16_t *y);
+
+/* out[j] = sum_i |(A W)_ij - B_ij| in FP64 for the k columns of W (host FP64
+ * d x k, column-major; d, k <= 64); B: device n x k (ldb >= n) or NULL. */
+int fct_l1_objectives(fct_ctx *ctx, const void *A, const void *B, int64_t n, int32_t d, int32_t k,
+                      int64_t lda, int64_t ldb, fct_dtype dt, const double *W, double *out);
 
 /* sum_i |A_i x - b_i| over all n rows (device reduction, FP64 result).
  * x: host double[d]; out: host double. */

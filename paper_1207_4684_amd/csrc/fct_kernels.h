@@ -7,8 +7,9 @@ namespace fctl1 {
 
 struct Pass1Args {
   const void* A;
-  const void* b;       // NULL when X = A
+  const void* b;       // NULL when X = A; else the k = q - d columns of B, X = [A, -B]
   int64_t lda;
+  int64_t ldb;         // leading dimension of B
   int64_t n;           // rows
   int64_t n_pad;       // s * ceil(n / s)
   int64_t rows_per_range;
@@ -99,8 +100,9 @@ __host__ __device__ int r2_padded(int r2);
 // Pass 2: lambda and per-workgroup FP64 partial sums of lambda.
 struct Pass2Args {
   const void* A;
-  const void* b;
+  const void* b;       // NULL, or the q - d columns of B (X = [A, -B])
   int64_t lda;
+  int64_t ldb;
   int64_t n;
   int32_t d;
   int32_t q;
@@ -149,7 +151,8 @@ hipError_t launch_select_replace(const float* lambda, int64_t n, int64_t s, uint
 hipError_t launch_probs_only(const SelectArgs& a, hipStream_t st);
 
 // Gather the kept rows of A and b (unscaled) into column-major outputs.
-hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, const int64_t* idx,
+hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, int32_t kb,
+                         int64_t ldb, const int64_t* idx,
                          const int64_t* S, int64_t cap, void* At, void* bt, int64_t ldat, bool f64,
                          hipStream_t st);
 
@@ -190,6 +193,13 @@ hipError_t launch_to_bf16(const float* x, int64_t count, uint16_t* y, hipStream_
 hipError_t launch_lowp_residual(const void* A, const void* b, int64_t lda, int64_t n, int d,
                                 bool f64, const double* R, double* x0, double* R_res, uint16_t* r,
                                 hipStream_t st);
+// sum_i |(A W)_ij - B_ij| for the k columns of W (B may be NULL), FP64.
+hipError_t launch_l1_objectives(const void* A, const void* B, int64_t lda, int64_t ldb, int64_t n,
+                                int d, int k, const double* W, bool f64, double* parts, int nparts,
+                                double* out, hipStream_t st);
+// Subspace approximation: per column j, the coreset without column j and column j.
+hipError_t launch_drop_column(const void* At, int64_t cap, int d, const int64_t* S, void* Aj,
+                              void* bj, bool f64, hipStream_t st);
 hipError_t launch_l1_objective(const void* A, const void* b, int64_t lda, int64_t n, int d,
                                const double* x, bool f64, double* parts, int nparts, double* out,
                                hipStream_t st);

@@ -300,8 +300,9 @@ void carve_sketch(C& cv, const Pass1Plan& p, int64_t n_pad, int q, int r1, size_
 
 int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64_t lda,
                fct_dtype dt, const void* b, int32_t s, int32_t r1, uint64_t seed, uint32_t flags,
-               void* Y, double* R, double** Yd_out, const Pass1Plan& p, int64_t row0g = 0) {
-  const int q = d + (b ? 1 : 0);
+               void* Y, double* R, double** Yd_out, const Pass1Plan& p, int64_t row0g = 0,
+               int32_t kb = 1, int64_t ldb = 0) {
+  const int q = d + (b ? kb : 0);
   const int64_t n_pad = (n + s - 1) / s * s;
   const size_t es = esize(dt);
   void* partials = cv.take<char>((size_t)p.nranges * q * r1 * (p.kind == 2 ? sizeof(float) : es));
@@ -317,6 +318,7 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.A = A;
   a.b = b;
   a.lda = lda;
+  a.ldb = ldb > 0 ? ldb : n;
   a.n = n;
   a.n_pad = n_pad;
   a.rows_per_range = p.rows_per_range;
@@ -336,7 +338,7 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   a.scale_h = 4.0f / sqrtf((float)s);
   a.bucket_span = p.bucket_span;
   const bool vec_ok = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0) &&
-                      (!b || (((uintptr_t)b & 15) == 0));
+                      (!b || (((uintptr_t)b & 15) == 0)) && (kb <= 1 || a.ldb % 4 == 0);
   prof_begin(c, 0);
   if (p.kind == 2) {
     HIP_TRY(launch_pass1_owner(a, p, vec_ok, c->stream));
@@ -382,8 +384,9 @@ struct ProbBufs {
 
 int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, int32_t d,
               int64_t lda, fct_dtype dt, const double* R, int32_t r2, uint64_t seed,
-              float* lambda, double* sum_lambda, uint32_t flags) {
-  const int q = d + (xb ? 1 : 0);
+              float* lambda, double* sum_lambda, uint32_t flags, int32_t kb = 1,
+              int64_t ldb = 0) {
+  const int q = d + (xb ? kb : 0);
   const int r2p = r2_padded(r2);
   double* Md = cv.take<double>((size_t)q * r2p);
   float* Mf = cv.take<float>((size_t)q * r2p);
@@ -398,6 +401,7 @@ int run_probs(fct_ctx* c, Carve& cv, const void* X, const void* xb, int64_t n, i
   a.A = X;
   a.b = xb;
   a.lda = lda;
+  a.ldb = ldb > 0 ? ldb : n;
   a.n = n;
   a.d = d;
   a.q = q;
@@ -782,7 +786,7 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
     if ((st = run_select(c, sub, lam, sl, n, (double)prm->s_out, prm->seed, cap, idx, w, S_dev)))
       return st;
   }
-  HIP_TRY(launch_gather(A, b, lda, d, idx, S_dev, cap, At, bt, cap, dt == FCT_F64, c->stream));
+  HIP_TRY(launch_gather(A, b, lda, d, 1, n, idx, S_dev, cap, At, bt, cap, dt == FCT_F64, c->stream));
   if (out && out->R)
     HIP_TRY(hipMemcpyAsync(out->R, R, (size_t)q * q * sizeof(double), hipMemcpyDeviceToDevice,
                            c->stream));
@@ -1381,7 +1385,7 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
                            S_dev + k, (uint32_t)k)))
         return st;
     }
-    HIP_TRY(launch_gather(A, b, lda, d, idx[k], S_dev + k, cap, const_cast<void*>(args[k].At),
+    HIP_TRY(launch_gather(A, b, lda, d, 1, n, idx[k], S_dev + k, cap, const_cast<void*>(args[k].At),
                           const_cast<void*>(args[k].bt), cap, dt == FCT_F64, c->stream));
   }
   std::memcpy(c->bpinned, args.data(), (size_t)K * sizeof(IrlsArgs));
@@ -1410,6 +1414,322 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
     if (stk != FCT_OK && first == FCT_OK) first = stk;
   }
   if (fl) return fl;
+  return first;
+}
+
+int fct_l1_objectives(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t d, int32_t k,
+                      int64_t lda, int64_t ldb, fct_dtype dt, const double* W, double* out) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!W || !out || k < 1 || d > 64 || k > 64 || (dt != FCT_F32 && dt != FCT_F64)) return FCT_ERR_BAD_ARG;
+  if (B && ldb < n) return FCT_ERR_BAD_ARG;
+  const int nparts = 512;
+  Measure m;
+  m.take<double>((size_t)d * k);
+  m.take<double>((size_t)nparts * k);
+  m.take<double>((size_t)k);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  double* Wd = cv.take<double>((size_t)d * k);
+  double* parts = cv.take<double>((size_t)nparts * k);
+  double* res = cv.take<double>((size_t)k);
+  // W (at most 64 x 64 doubles) through the resizable pinned block
+  if ((st = batch_ensure_aux(c, (size_t)d * k * sizeof(double)))) return st;
+  std::memcpy(c->bpinned, W, (size_t)d * k * sizeof(double));
+  HIP_TRY(hipMemcpyAsync(Wd, c->bpinned, (size_t)d * k * sizeof(double), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(launch_l1_objectives(A, B, lda, ldb, n, d, k, Wd, dt == FCT_F64, parts, nparts, res,
+                               c->stream));
+  HIP_TRY(hipMemcpyAsync(c->bpinned, res, (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  const int fl = read_flags(c);
+  std::memcpy(out, c->bpinned, (size_t)k * sizeof(double));
+  return fl;
+}
+
+int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t d, int32_t k,
+                    int64_t lda, int64_t ldb, fct_dtype dt, double eps, const fct_params* prm_in,
+                    double* W, double* obj, int64_t* S_out, int32_t* status, double* R_out,
+                    float* lambda_out) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!B || !W || !status || !prm_in || k < 1 || d > 64 || ldb < n ||
+      (dt != FCT_F32 && dt != FCT_F64))
+    return FCT_ERR_BAD_ARG;
+  const int q = d + k;
+  if (q > 88) return FCT_ERR_BAD_ARG;
+  fct_params prm = *prm_in;
+  if (prm.s_out <= 0) {
+    if (!(eps > 0.0)) return FCT_ERR_BAD_ARG;
+    prm.s_out = (int64_t)std::ceil(20.0 * q / eps);
+  }
+  if ((st = check_params(&prm, q))) return st;
+  const int iters = prm.irls_iters > 0 ? prm.irls_iters : 80;
+  int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
+  if (cap > n) cap = n;
+  const size_t es = esize(dt);
+  const int64_t n_pad = (n + prm.s - 1) / prm.s * prm.s;
+  int perr = 0;
+  const Pass1Plan plan = make_pass1_plan(c, n_pad, q, prm.s, prm.r1, es, prm.flags, &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  auto layout = [&](auto& cv) {
+    cv.template take<double>((size_t)q * q);
+    cv.template take<float>((size_t)n);
+    cv.template take<double>(1);
+    cv.template take<int64_t>(1);
+    cv.template take<char>((size_t)cap * d * es);
+    cv.template take<char>((size_t)cap * k * es);
+    cv.template take<double>((size_t)cap);
+    cv.template take<int64_t>((size_t)cap);
+    cv.template take<char>((size_t)k * sizeof(IrlsArgs));
+    cv.template take<double>((size_t)k * 72);
+    for (int j = 0; j < k; ++j) {
+      cv.template take<double>(irls_batched_work_doubles(d));
+      cv.template take<double>(72);
+      cv.template take<int>(4);
+    }
+  };
+  Measure m;
+  layout(m);
+  Measure ma, mb, mc;
+  carve_sketch(ma, plan, n_pad, q, prm.r1, es, true);
+  carve_probs(mb, c, q, prm.r2, n, dt == FCT_F64 ? kPass2F64 : kPass2F32);
+  carve_select(mc, n);
+  if ((st = ensure_scratch(c, m.off + std::max(ma.off, std::max(mb.off, mc.off)) + 1280))) return st;
+  const size_t pin = std::max((size_t)k * sizeof(IrlsArgs), (size_t)k * 72 * sizeof(double));
+  if ((st = batch_ensure_aux(c, pin))) return st;
+  Carve cv(c->scratch);
+  double* R = cv.take<double>((size_t)q * q);
+  float* lam = cv.take<float>((size_t)n);
+  double* sl = cv.take<double>(1);
+  int64_t* S_dev = cv.take<int64_t>(1);
+  char* At = cv.take<char>((size_t)cap * d * es);
+  char* Bt = cv.take<char>((size_t)cap * k * es);
+  double* w = cv.take<double>((size_t)cap);
+  int64_t* idx = cv.take<int64_t>((size_t)cap);
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>((size_t)k * sizeof(IrlsArgs)));
+  double* out_dev = cv.take<double>((size_t)k * 72);
+  std::vector<IrlsArgs> args((size_t)k);
+  for (int j = 0; j < k; ++j) {
+    IrlsArgs& a = args[j];
+    double* work = cv.take<double>(irls_batched_work_doubles(d));
+    double* outv = cv.take<double>(72);
+    a.status = cv.take<int>(4);
+    a.At = At;
+    a.bt = Bt + (size_t)j * cap * es;
+    a.w = w;
+    a.S_dev = S_dev;
+    a.cap = cap;
+    a.ldat = cap;
+    a.d = d;
+    a.iters = iters;
+    a.row_target = 1 << 30;
+    a.part = work;
+    a.bar = irls_batched_bar(work, d);
+    a.x_out = outv;
+    a.obj_out = outv + 64;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_sketch(c, sub, A, n, d, lda, dt, B, prm.s, prm.r1, prm.seed, prm.flags, nullptr,
+                         R, nullptr, plan, 0, k, ldb)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_probs(c, sub, A, B, n, d, lda, dt, R, prm.r2, prm.seed, lam, sl, prm.flags, k,
+                        ldb)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_select(c, sub, lam, sl, n, (double)prm.s_out, prm.seed, cap, idx, w, S_dev)))
+      return st;
+  }
+  HIP_TRY(launch_gather(A, B, lda, d, k, ldb, idx, S_dev, cap, At, Bt, cap, dt == FCT_F64,
+                        c->stream));
+  if (R_out)
+    HIP_TRY(hipMemcpyAsync(R_out, R, (size_t)q * q * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (lambda_out)
+    HIP_TRY(hipMemcpyAsync(lambda_out, lam, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  std::memcpy(c->bpinned, args.data(), (size_t)k * sizeof(IrlsArgs));
+  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)k * sizeof(IrlsArgs), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_begin(c, 2);
+  HIP_TRY(launch_irls_batched(args_dev, k, dt == FCT_F64, c->stream));
+  prof_end(c, 2);
+  hipLaunchKernelGGL(batch_collect_kernel, dim3(k), dim3(64), 0, c->stream, args_dev, k, out_dev);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->bpinned, out_dev, (size_t)k * 72 * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  const int fl = read_flags(c);
+  const double* h = reinterpret_cast<const double*>(c->bpinned);
+  int first = FCT_OK;
+  const int64_t S = (int64_t)h[65];
+  if (S_out) *S_out = S;
+  for (int j = 0; j < k; ++j) {
+    const double* row = h + (size_t)j * 72;
+    int stj = (int)row[66];
+    if (S > cap) stj = FCT_ERR_CAPACITY;
+    status[j] = stj;
+    for (int i = 0; i < d; ++i) W[(size_t)j * d + i] = row[i];
+    if (obj) obj[j] = row[64];
+    if (stj != FCT_OK && first == FCT_OK) first = stj;
+  }
+  if (fl) return fl;
+  return first;
+}
+
+int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fct_dtype dt,
+                double eps, const fct_params* prm_in, double* W, double* err, int32_t* j_star,
+                int64_t* S_out, int32_t* status, double* R_out, float* lambda_out) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  if (!W || !err || !j_star || !status || !prm_in || d < 2 || d > 64 ||
+      (dt != FCT_F32 && dt != FCT_F64))
+    return FCT_ERR_BAD_ARG;
+  const int q = d;
+  fct_params prm = *prm_in;
+  if (prm.s_out <= 0) {
+    if (!(eps > 0.0)) return FCT_ERR_BAD_ARG;
+    prm.s_out = (int64_t)std::ceil(20.0 * q / eps);
+  }
+  if ((st = check_params(&prm, q))) return st;
+  const int iters = prm.irls_iters > 0 ? prm.irls_iters : 80;
+  int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
+  if (cap > n) cap = n;
+  const size_t es = esize(dt);
+  const int64_t n_pad = (n + prm.s - 1) / prm.s * prm.s;
+  int perr = 0;
+  const Pass1Plan plan = make_pass1_plan(c, n_pad, q, prm.s, prm.r1, es, prm.flags, &perr);
+  if (perr) return FCT_ERR_BAD_ARG;
+  const int dj = d - 1;
+  auto layout = [&](auto& cv) {
+    cv.template take<double>((size_t)q * q);
+    cv.template take<float>((size_t)n);
+    cv.template take<double>(1);
+    cv.template take<int64_t>(1);
+    cv.template take<char>((size_t)cap * d * es);
+    cv.template take<char>((size_t)cap * dj * d * es);
+    cv.template take<char>((size_t)cap * d * es);
+    cv.template take<double>((size_t)cap);
+    cv.template take<int64_t>((size_t)cap);
+    cv.template take<char>((size_t)d * sizeof(IrlsArgs));
+    cv.template take<double>((size_t)d * 72);
+    for (int j = 0; j < d; ++j) {
+      cv.template take<double>(irls_batched_work_doubles(dj));
+      cv.template take<double>(72);
+      cv.template take<int>(4);
+    }
+  };
+  Measure m;
+  layout(m);
+  Measure ma, mb, mc;
+  carve_sketch(ma, plan, n_pad, q, prm.r1, es, true);
+  carve_probs(mb, c, q, prm.r2, n, dt == FCT_F64 ? kPass2F64 : kPass2F32);
+  carve_select(mc, n);
+  if ((st = ensure_scratch(c, m.off + std::max(ma.off, std::max(mb.off, mc.off)) + 1280))) return st;
+  const size_t pin = std::max((size_t)d * sizeof(IrlsArgs), (size_t)d * 72 * sizeof(double));
+  if ((st = batch_ensure_aux(c, pin))) return st;
+  Carve cv(c->scratch);
+  double* R = cv.take<double>((size_t)q * q);
+  float* lam = cv.take<float>((size_t)n);
+  double* sl = cv.take<double>(1);
+  int64_t* S_dev = cv.take<int64_t>(1);
+  char* At = cv.take<char>((size_t)cap * d * es);
+  char* Aj = cv.take<char>((size_t)cap * dj * d * es);
+  char* bj = cv.take<char>((size_t)cap * d * es);
+  double* w = cv.take<double>((size_t)cap);
+  int64_t* idx = cv.take<int64_t>((size_t)cap);
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>((size_t)d * sizeof(IrlsArgs)));
+  double* out_dev = cv.take<double>((size_t)d * 72);
+  std::vector<IrlsArgs> args((size_t)d);
+  for (int j = 0; j < d; ++j) {
+    IrlsArgs& a = args[j];
+    double* work = cv.take<double>(irls_batched_work_doubles(dj));
+    double* outv = cv.take<double>(72);
+    a.status = cv.take<int>(4);
+    a.At = Aj + (size_t)j * cap * dj * es;
+    a.bt = bj + (size_t)j * cap * es;
+    a.w = w;
+    a.S_dev = S_dev;
+    a.cap = cap;
+    a.ldat = cap;
+    a.d = dj;
+    a.iters = iters;
+    a.row_target = 1 << 30;
+    a.part = work;
+    a.bar = irls_batched_bar(work, dj);
+    a.x_out = outv;
+    a.obj_out = outv + 64;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_sketch(c, sub, A, n, d, lda, dt, nullptr, prm.s, prm.r1, prm.seed, prm.flags,
+                         nullptr, R, nullptr, plan)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_probs(c, sub, A, nullptr, n, d, lda, dt, R, prm.r2, prm.seed, lam, sl,
+                        prm.flags)))
+      return st;
+  }
+  {
+    Carve sub(cv.base);
+    sub.off = cv.off;
+    if ((st = run_select(c, sub, lam, sl, n, (double)prm.s_out, prm.seed, cap, idx, w, S_dev)))
+      return st;
+  }
+  HIP_TRY(launch_gather(A, nullptr, lda, d, 0, n, idx, S_dev, cap, At, nullptr, cap,
+                        dt == FCT_F64, c->stream));
+  HIP_TRY(launch_drop_column(At, cap, d, S_dev, Aj, bj, dt == FCT_F64, c->stream));
+  if (R_out)
+    HIP_TRY(hipMemcpyAsync(R_out, R, (size_t)q * q * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (lambda_out)
+    HIP_TRY(hipMemcpyAsync(lambda_out, lam, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice,
+                           c->stream));
+  std::memcpy(c->bpinned, args.data(), (size_t)d * sizeof(IrlsArgs));
+  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)d * sizeof(IrlsArgs), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  prof_begin(c, 2);
+  HIP_TRY(launch_irls_batched(args_dev, d, dt == FCT_F64, c->stream));
+  prof_end(c, 2);
+  hipLaunchKernelGGL(batch_collect_kernel, dim3(d), dim3(64), 0, c->stream, args_dev, d, out_dev);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->bpinned, out_dev, (size_t)d * 72 * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  int fl = read_flags(c);
+  if (fl) return fl;
+  const double* h = reinterpret_cast<const double*>(c->bpinned);
+  int first = FCT_OK;
+  const int64_t S = (int64_t)h[65];
+  if (S_out) *S_out = S;
+  // column j of W: the solution of regression j with -1 inserted at row j
+  for (int j = 0; j < d; ++j) {
+    const double* row = h + (size_t)j * 72;
+    int stj = (int)row[66];
+    if (S > cap) stj = FCT_ERR_CAPACITY;
+    status[j] = stj;
+    for (int i = 0, o = 0; i < d; ++i) W[(size_t)j * d + i] = i == j ? -1.0 : row[o++];
+    if (stj != FCT_OK && first == FCT_OK) first = stj;
+  }
+  // the error of every candidate hyperplane over all rows: ||A w_j||_1
+  if ((st = fct_l1_objectives(c, A, nullptr, n, d, d, lda, n, dt, W, err))) return st;
+  int best = 0;
+  for (int j = 1; j < d; ++j)
+    if (err[j] < err[best]) best = j;
+  *j_star = best;
   return first;
 }
 

@@ -123,3 +123,110 @@ hipError_t launch_lowp_residual(const void* A, const void* b, int64_t lda, int64
 }
 
 }  // namespace fctl1
+
+namespace fctl1 {
+
+// sum_i |(A W)_ij - B_ij| for the k columns of W (d x k, column-major,
+// FP64; B optional, n x k with leading dimension ldb), in FP64.  The grid's
+// y index takes 8 consecutive columns; a thread takes rows in a grid stride
+// and keeps its 8 sums in registers; a workgroup's sums go to
+// parts[blockIdx.x][j] after a fixed-order reduction.
+template <typename T>
+__global__ void __launch_bounds__(256) l1_objectives_kernel(const T* __restrict__ A,
+                                                            const T* __restrict__ B, int64_t lda,
+                                                            int64_t ldb, int64_t n, int d, int k,
+                                                            const double* __restrict__ W,
+                                                            double* __restrict__ parts) {
+  __shared__ double red[4][8];
+  const int j0 = blockIdx.y * 8;
+  double s[8];
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) s[jj] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double r[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+      r[jj] = (B && j0 + jj < k) ? -(double)B[i + (int64_t)(j0 + jj) * ldb] : 0.0;
+    for (int c = 0; c < d; ++c) {
+      const double a = (double)A[i + (int64_t)c * lda];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj)
+        if (j0 + jj < k) r[jj] = fma(a, W[c + (int64_t)(j0 + jj) * d], r[jj]);
+    }
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) s[jj] += fabs(r[jj]);
+  }
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) {
+    const double v = wave_sum_dpp(s[jj]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][jj] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && j0 + (int)threadIdx.x < k)
+    parts[(int64_t)blockIdx.x * k + j0 + threadIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// out[j] = sum over the workgroups of parts[.][j], in workgroup order
+__global__ void objectives_sum_kernel(const double* __restrict__ parts, int nparts, int k,
+                                      double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += parts[(int64_t)p * k + j];
+  out[j] = s;
+}
+
+hipError_t launch_l1_objectives(const void* A, const void* B, int64_t lda, int64_t ldb, int64_t n,
+                                int d, int k, const double* W, bool f64, double* parts, int nparts,
+                                double* out, hipStream_t st) {
+  const dim3 grid((unsigned)nparts, (unsigned)((k + 7) / 8));
+  if (f64)
+    hipLaunchKernelGGL(l1_objectives_kernel<double>, grid, dim3(256), 0, st, (const double*)A,
+                       (const double*)B, lda, ldb, n, d, k, W, parts);
+  else
+    hipLaunchKernelGGL(l1_objectives_kernel<float>, grid, dim3(256), 0, st, (const float*)A,
+                       (const float*)B, lda, ldb, n, d, k, W, parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(objectives_sum_kernel, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, st, parts,
+                     nparts, k, out);
+  return hipGetLastError();
+}
+
+// The d designs of the constrained regressions of subspace approximation:
+// for column j, the coreset's other d - 1 columns (in order) into
+// Aj[j][.] and column j into bj[j][.] (each cap rows, leading dimension cap).
+template <typename T>
+__global__ void __launch_bounds__(256) drop_column_kernel(const T* __restrict__ At, int64_t cap, int d,
+                                                          const int64_t* __restrict__ S,
+                                                          T* __restrict__ Aj, T* __restrict__ bj) {
+  const int j = blockIdx.y;
+  const int64_t cnt = min(*S, cap);
+  T* dst = Aj + (int64_t)j * cap * (d - 1);
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < cnt;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    for (int c = 0, o = 0; c < d; ++c) {
+      const T v = At[r + (int64_t)c * cap];
+      if (c == j) bj[(int64_t)j * cap + r] = v;
+      else dst[r + (int64_t)(o++) * cap] = v;
+    }
+  }
+}
+
+hipError_t launch_drop_column(const void* At, int64_t cap, int d, const int64_t* S, void* Aj,
+                              void* bj, bool f64, hipStream_t st) {
+  int64_t gx = (cap + 255) / 256;
+  if (gx > 1024) gx = 1024;
+  const dim3 grid((unsigned)gx, (unsigned)d);
+  if (f64)
+    hipLaunchKernelGGL(drop_column_kernel<double>, grid, dim3(256), 0, st, (const double*)At, cap,
+                       d, S, (double*)Aj, (double*)bj);
+  else
+    hipLaunchKernelGGL(drop_column_kernel<float>, grid, dim3(256), 0, st, (const float*)At, cap,
+                       d, S, (float*)Aj, (float*)bj);
+  return hipGetLastError();
+}
+
+}  // namespace fctl1

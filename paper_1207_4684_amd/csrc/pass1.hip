@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(1024) pass1_kernel(Pass1Args a) {
         T x = T(0);
         if (inrange) {
           if (gc < a.d) x = reinterpret_cast<const T*>(a.A)[j + (int64_t)gc * a.lda];
-          else x = -reinterpret_cast<const T*>(a.b)[j];
+          else x = -reinterpret_cast<const T*>(a.b)[j + (int64_t)(gc - a.d) * a.ldb];
         }
         const T u = T(sg) * x;
         tile[col * TP + tpad(t)] = u;

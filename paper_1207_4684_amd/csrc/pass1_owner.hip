@@ -84,7 +84,7 @@ __host__ __device__ inline OwnLayout own_layout(int span) {
 __device__ __forceinline__ void own_load(const Pass1Args& a, int gc, int64_t tl, int lane, bool vok,
                                          float (&v)[16]) {
   const float* p = gc < a.d ? reinterpret_cast<const float*>(a.A) + (int64_t)gc * a.lda
-                            : reinterpret_cast<const float*>(a.b);
+                            : reinterpret_cast<const float*>(a.b) + (int64_t)(gc - a.d) * a.ldb;
   if (vok && tl + kORowsWave <= a.n) {  // the wave's whole span is inside X (wave-uniform)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -150,7 +150,7 @@ __device__ __forceinline__ void own_produce(const Pass1Args& a, unsigned char* s
                                            int L, const uint32_t (&sm)[16], const float (&cI)[16],
                                            const float (&cH)[16], const uint32_t (&slI)[16],
                                            const uint32_t (&slH)[16], float (&v)[16]) {
-  const uint32_t negb = (a.b && c0 + col == a.d) ? 0x80000000u : 0u;
+  const uint32_t negb = (a.b && c0 + col >= a.d) ? 0x80000000u : 0u;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     v[r] = __uint_as_float(xor3(__float_as_uint(v[r]), sm[r], negb));

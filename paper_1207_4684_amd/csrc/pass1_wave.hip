@@ -68,7 +68,7 @@ __device__ __forceinline__ void load_group(const Pass1Args& a, int c0, int cs, i
   }
   const int gc = c0 + col;
   const float* p = gc < a.d ? reinterpret_cast<const float*>(a.A) + (int64_t)gc * a.lda
-                            : reinterpret_cast<const float*>(a.b);
+                            : reinterpret_cast<const float*>(a.b) + (int64_t)(gc - a.d) * a.ldb;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int64_t j = tile + 4 * L + 64 * k;
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_wave_kernel(Pass1Args a, in
       const bool cact = colr < cs;
       const int col = cact ? colr : cs - 1;  // idle lanes (masked off at the adds) stay in bounds
       // sign D(j) (and the minus of the b column) as a sign-bit xor
-      const uint32_t negb = (cact && c0 + col == a.d) ? 0x80000000u : 0u;
+      const uint32_t negb = (cact && a.b && c0 + col >= a.d) ? 0x80000000u : 0u;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         uint32_t bits = 0;
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kWaves * 64) pass1_block_kernel(Pass1Args a, i
       const int col = cact ? colr : cs - 1;  // idle lanes (masked off at the adds) stay in bounds
       // sign D(j) (bit 31 of the I entry) and the minus of the b column as a
       // sign-bit xor, then the I-half copies: rows t = 4 L + i + 64 k
-      const uint32_t negb = (cact && c0 + col == a.d) ? 0x80000000u : 0u;
+      const uint32_t negb = (cact && a.b && c0 + col >= a.d) ? 0x80000000u : 0u;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int t0 = 4 * L + 64 * k;

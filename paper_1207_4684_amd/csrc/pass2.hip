@@ -143,7 +143,8 @@ __global__ void __launch_bounds__(kP2Threads) pass2_valu_kernel(Pass2Args a) {
 #pragma unroll
     for (int j = 0; j < R2P; ++j) acc[j] = TA(0);
     for (int col = 0; col < a.q; ++col) {
-      TA x = (col < a.d) ? Load<TX>::get(a.A, i + (int64_t)col * a.lda) : -Load<TX>::get(a.b, i);
+      TA x = (col < a.d) ? Load<TX>::get(a.A, i + (int64_t)col * a.lda)
+                         : -Load<TX>::get(a.b, i + (int64_t)(col - a.d) * a.ldb);
 #pragma unroll
       for (int j = 0; j < R2P; ++j) acc[j] = FmaT<TA>::fma(x, M[col * R2P + j], acc[j]);
     }
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
   const float* __restrict__ A = reinterpret_cast<const float*>(a.A);
   const float* __restrict__ bv = reinterpret_cast<const float*>(a.b);
   const bool vec = (a.lda & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
-                   (reinterpret_cast<uintptr_t>(bv) & 15) == 0;
+                   (reinterpret_cast<uintptr_t>(bv) & 15) == 0 && (a.q - a.d <= 1 || (a.ldb & 3) == 0);
   // A operand: M[k][m], k = 4 ks + lane / 16, m = lane % 16 + 16 mt
   float am[MT][KS];
 #pragma unroll
@@ -229,7 +230,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
       const int c = 4 * ks + g;
       float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (c < a.q) {
-        const float* col = c < a.d ? A + (int64_t)c * a.lda : bv;
+        const float* col = c < a.d ? A + (int64_t)c * a.lda : bv + (int64_t)(c - a.d) * a.ldb;
         if (vec && rb + 3 < a.n) {
           x4 = *reinterpret_cast<const float4*>(col + rb);
         } else {
@@ -238,7 +239,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
           if (rb + 2 < a.n) x4.z = col[rb + 2];
           if (rb + 3 < a.n) x4.w = col[rb + 3];
         }
-        if (c == a.d) x4 = make_float4(-x4.x, -x4.y, -x4.z, -x4.w);
+        if (c >= a.d) x4 = make_float4(-x4.x, -x4.y, -x4.z, -x4.w);
       }
       xv[ks] = x4;
     }
@@ -293,7 +294,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
   const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(a.A);
   const uint16_t* __restrict__ bv = reinterpret_cast<const uint16_t*>(a.b);
   const bool vec = (a.lda & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 7) == 0 &&
-                   (reinterpret_cast<uintptr_t>(bv) & 7) == 0;
+                   (reinterpret_cast<uintptr_t>(bv) & 7) == 0 && (a.q - a.d <= 1 || (a.ldb & 3) == 0);
   // A operand: M[k][m] as BF16, k = 16 ks + 4 (lane / 16) + j, m = lane % 16 + 16 mt
   s16x4 am[MT][KS];
 #pragma unroll
@@ -323,7 +324,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
         const int c = 16 * ks + 4 * g + j;
         uint2 x4 = make_uint2(0u, 0u);
         if (c < a.q) {
-          const uint16_t* col = c < a.d ? A + (int64_t)c * a.lda : bv;
+          const uint16_t* col = c < a.d ? A + (int64_t)c * a.lda : bv + (int64_t)(c - a.d) * a.ldb;
           if (vec && rb + 3 < a.n) {
             x4 = *reinterpret_cast<const uint2*>(col + rb);
           } else {
@@ -331,7 +332,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
             const uint32_t e2 = rb + 2 < a.n ? col[rb + 2] : 0u, e3 = rb + 3 < a.n ? col[rb + 3] : 0u;
             x4 = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
           }
-          if (c == a.d) x4 = make_uint2(x4.x ^ 0x80008000u, x4.y ^ 0x80008000u);
+          if (c >= a.d) x4 = make_uint2(x4.x ^ 0x80008000u, x4.y ^ 0x80008000u);
         }
         xv[ks][j] = x4;
       }

@@ -407,7 +407,7 @@ hipError_t launch_probs_only(const SelectArgs& a, hipStream_t st) {
 
 template <typename T>
 __global__ void gather_kernel(const T* __restrict__ A, const T* __restrict__ b, int64_t lda,
-                              int32_t d, const int64_t* __restrict__ idx,
+                              int32_t d, int32_t kb, int64_t ldb, const int64_t* __restrict__ idx,
                               const int64_t* __restrict__ S, int64_t cap, T* __restrict__ At,
                               T* __restrict__ bt, int64_t ldat) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,19 +415,22 @@ __global__ void gather_kernel(const T* __restrict__ A, const T* __restrict__ b, 
   if (k >= cnt) return;
   const int64_t i = idx[k];
   for (int c = 0; c < d; ++c) At[k + (int64_t)c * ldat] = A[i + (int64_t)c * lda];
-  bt[k] = b[i];
+  for (int c = 0; c < kb; ++c) bt[k + (int64_t)c * ldat] = b[i + (int64_t)c * ldb];
 }
 
-hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, const int64_t* idx,
-                         const int64_t* S, int64_t cap, void* At, void* bt, int64_t ldat, bool f64,
-                         hipStream_t st) {
+hipError_t launch_gather(const void* A, const void* b, int64_t lda, int32_t d, int32_t kb,
+                         int64_t ldb, const int64_t* idx, const int64_t* S, int64_t cap, void* At,
+                         void* bt, int64_t ldat, bool f64, hipStream_t st) {
   const unsigned grid = (unsigned)((cap + 255) / 256);
+  if (!b) kb = 0;
   if (f64)
     hipLaunchKernelGGL(gather_kernel<double>, dim3(grid), dim3(256), 0, st, (const double*)A,
-                       (const double*)b, lda, d, idx, S, cap, (double*)At, (double*)bt, ldat);
+                       (const double*)b, lda, d, kb, ldb, idx, S, cap, (double*)At, (double*)bt,
+                       ldat);
   else
     hipLaunchKernelGGL(gather_kernel<float>, dim3(grid), dim3(256), 0, st, (const float*)A,
-                       (const float*)b, lda, d, idx, S, cap, (float*)At, (float*)bt, ldat);
+                       (const float*)b, lda, d, kb, ldb, idx, S, cap, (float*)At, (float*)bt,
+                       ldat);
   return hipGetLastError();
 }
 

@@ -82,6 +82,14 @@ def _load():
         "fct_to_bf16": (ctypes.c_int, [P, P, I64, P]),
         "fct_lowp_residual": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, P, P]),
         "l1_select_draw": (ctypes.c_int, [P, P, P, I64, I64, U64, I32, I32, I64, P, P, PI64]),
+        "l1_regress_mrhs": (ctypes.c_int, [P, P, P, I64, I32, I32, I64, I64, ctypes.c_int, D,
+                                           ctypes.POINTER(fct_params), PD, PD, PI64,
+                                           ctypes.POINTER(ctypes.c_int32), P, P]),
+        "l1_subspace": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, D,
+                                       ctypes.POINTER(fct_params), PD, PD,
+                                       ctypes.POINTER(ctypes.c_int32), PI64,
+                                       ctypes.POINTER(ctypes.c_int32), P, P]),
+        "fct_l1_objectives": (ctypes.c_int, [P, P, P, I64, I32, I32, I64, I64, ctypes.c_int, PD, PD]),
         "l1_regress_multi": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, D,
                                             ctypes.POINTER(fct_params), I32, I32, PD, PD, PI64,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -108,7 +116,8 @@ EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream
             "l1_coreset", "l1_regress", "fct_rng_words", "fct_pi1_streams", "fct_fwht",
             "fct_to_bf16", "fct_lowp_residual", "fct_l1_objective", "l1_solve", "l1_select",
             "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option",
-            "l1_select_draw", "l1_regress_multi")
+            "l1_select_draw", "l1_regress_multi", "l1_regress_mrhs", "l1_subspace",
+            "fct_l1_objectives")
 
 
 def _check(st: int, where: str):
@@ -378,6 +387,59 @@ def l1_regress_multi(ctx, A, b, prm, K, mode=FCT_SAMPLE_BERNOULLI, eps=0.05):
     if st not in (0, -4, -6, -5) or (st != 0 and all(v == 0 for v in status)):
         _check(st, "l1_regress_multi")
     return (np.array(x[:]).reshape(K, d), list(obj), list(S), list(status), st)
+
+
+def l1_regress_mrhs(ctx, A, B, prm, eps=0.05, R_out=None, lambda_out=None):
+    """Multiple l1 regression: A (d, n) and B (k, n) device tensors (column-major
+    storage); returns (W (d, k) numpy, obj, S, status, return status).  R_out
+    ((q, q) FP64 device, filled column-major) and lambda_out ((n,) FP32) are
+    optional."""
+    import numpy as np
+    n, d, lda = _cm(A)
+    nb, k, ldb = _cm(B)
+    if nb != n:
+        raise ValueError("A and B need the same rows")
+    W = (ctypes.c_double * (d * k))()
+    obj = (ctypes.c_double * k)()
+    S = ctypes.c_int64()
+    status = (ctypes.c_int32 * k)()
+    st = ctx.call(_lib.l1_regress_mrhs, ctx.handle, _ptr(A), _ptr(B), n, d, k, lda, ldb, _dt(A), eps,
+                  ctypes.byref(prm), W, obj, ctypes.byref(S), status, _ptr(R_out), _ptr(lambda_out))
+    if st not in (0, -4, -6, -5) or (st != 0 and all(v == 0 for v in status)):
+        _check(st, "l1_regress_mrhs")
+    return np.array(W[:]).reshape(k, d).T, list(obj), S.value, list(status), st
+
+
+def l1_subspace(ctx, A, prm, eps=0.05, R_out=None, lambda_out=None):
+    """l1 subspace approximation of the rows of A ((d, n) device tensor):
+    (W (d, d) numpy with W[j, j] = -1, err (d,), j_star, S, status, return
+    status); R_out and lambda_out as for l1_regress_mrhs."""
+    import numpy as np
+    n, d, lda = _cm(A)
+    W = (ctypes.c_double * (d * d))()
+    err = (ctypes.c_double * d)()
+    js = ctypes.c_int32()
+    S = ctypes.c_int64()
+    status = (ctypes.c_int32 * d)()
+    st = ctx.call(_lib.l1_subspace, ctx.handle, _ptr(A), n, d, lda, _dt(A), eps, ctypes.byref(prm),
+                  W, err, ctypes.byref(js), ctypes.byref(S), status, _ptr(R_out), _ptr(lambda_out))
+    if st not in (0, -4, -6, -5) or (st != 0 and all(v == 0 for v in status)):
+        _check(st, "l1_subspace")
+    return np.array(W[:]).reshape(d, d).T, np.array(err[:]), js.value, S.value, list(status), st
+
+
+def fct_l1_objectives(ctx, A, B, W):
+    """sum_i |(A W)_ij - B_ij| for the columns of W ((d, k) numpy); B (k, n) or None."""
+    import numpy as np
+    n, d, lda = _cm(A)
+    W = np.asarray(W, dtype=np.float64)
+    k = W.shape[1]
+    ldb = _cm(B)[2] if B is not None else n
+    Wc = (ctypes.c_double * (d * k))(*W.T.reshape(-1).tolist())
+    out = (ctypes.c_double * k)()
+    _check(ctx.call(_lib.fct_l1_objectives, ctx.handle, _ptr(A), _ptr(B), n, d, k, lda, ldb, _dt(A),
+                    Wc, out), "fct_l1_objectives")
+    return np.array(out[:])
 
 
 def l1_solve(ctx, At, bt, w, iters=0):
