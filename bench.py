@@ -392,6 +392,47 @@ def bf16_error_report(F, torch, ctx, w, Ad, bd, Al, bl):
     return out
 
 
+def bench_mrhs_subspace(F, torch, ctx, flush, k: int = 8):
+    """Multiple l1 regression with k right-hand sides and l1 subspace
+    approximation on the tall generator (4,194,304 rows): one sketch and
+    sampling pass for all the regressions against k (or d) single ones."""
+    import synth
+    w = synth.TALL
+    A, b, _ = synth.generate(w, threads=min(16, len(os.sched_getaffinity(0))))
+    Ad, bd = torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda()
+    rng = np.random.default_rng(1)
+    # k right-hand sides: b, and planted fits A x_j with Laplace noise and 2%
+    # Cauchy outliers
+    Bh = np.empty((k, w.n), dtype=np.float32)
+    Bh[0] = b
+    xs = rng.standard_normal((w.d, k - 1))
+    Bh[1:] = (A.T.astype(np.float64) @ xs).T + rng.laplace(0, 0.1, (k - 1, w.n))
+    out_rows = rng.choice(w.n, w.n // 50, replace=False)
+    Bh[1:, out_rows] = 1e3 * rng.standard_cauchy((k - 1, out_rows.size))
+    Bd = torch.from_numpy(Bh).cuda()
+    del A, b, Bh
+    q = w.d + k
+    prm = F.params(s=w.s, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
+    out = {"workload": f"{w.name}, {k} right-hand sides", "k": k}
+    t_m, res = timed_steps(torch, lambda: F.l1_regress_mrhs(ctx, Ad, Bd, prm, eps=w.eps), 3, 1, flush)
+    t_s, _ = timed_steps(torch, lambda: [F.l1_regress(ctx, Ad, Bd[j], prm, eps=w.eps) for j in range(k)],
+                         3, 1, flush)
+    out.update({"mrhs_ms": round(statistics.median(t_m) * 1e3, 4),
+                "single_calls_ms": round(statistics.median(t_s) * 1e3, 4),
+                "speedup": round(statistics.median(t_s) / statistics.median(t_m), 3),
+                "coreset_rows": int(res[2]),
+                "algorithmic_GBps": round(2 * w.n * (w.d + k) * 4 / statistics.median(t_m) / 1e9, 1)})
+    # subspace approximation of the points [A, b] (d + 1 = 33 coordinates)
+    X = torch.cat([Ad, bd[None, :]], dim=0).contiguous()
+    prs = F.params(s=w.s, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed)
+    t_p, rp = timed_steps(torch, lambda: F.l1_subspace(ctx, X, prs, eps=w.eps), 3, 1, flush)
+    out.update({"subspace_points": f"{w.n} x {w.d + 1}", "subspace_ms": round(statistics.median(t_p) * 1e3, 4),
+                "subspace_j_star": int(rp[2]), "subspace_coreset_rows": int(rp[3])})
+    del Ad, bd, Bd, X
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(F, ctx, count: int, steps: int):
     """The batching workload: `count` instances of uneven n and d solved in one
     batch (captured graph, block size s from the library's rule per d), against the same
@@ -470,6 +511,8 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256, help="instances of the batching workload (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-mrhs", dest="mrhs", action="store_false",
+                    help="skip the multiple-regression and subspace timings")
     ap.add_argument("--multi", type=int, default=16,
                     help="coresets per sampling pass timed on the headline workload (0 = skip)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 26, help="rows of the CPU baseline's sample")
@@ -512,6 +555,7 @@ def main():
                                     ref=not args.skip_ref and name != "precision",
                                     err_report=name == "precision")
     batched = bench_batched(F, ctx, args.batch, args.batch_steps) if args.batch > 0 else None
+    mrhs = bench_mrhs_subspace(F, torch, ctx, flush) if args.mrhs else None
     del flush
     ctx.close()
     torch.cuda.empty_cache()
@@ -564,6 +608,7 @@ def main():
         "end_to_end": head,
         "workloads": extras,
         "batched": batched,
+        "multiple_rhs_and_subspace": mrhs,
     }
     print(json.dumps(rec))
 
