@@ -139,3 +139,60 @@ def pi1_dense(n: int, s: int, r1: int, seed: int, sign_flip: bool = True,
     D = np.diag(philox.signs(seed, n_pad, instance) if sign_flip else np.ones(n_pad))
     P = 4.0 * B @ C @ Ht @ D
     return P[:, :n]
+
+
+def fct2_scale(r1: int, s: int, t: int) -> float:
+    """The constant of FCT2 (section "FCT2 Construction"): 8/r1 sqrt(pi t / (2 s))."""
+    return 8.0 / r1 * np.sqrt(np.pi * t / (2.0 * s))
+
+
+def fct2_apply(X, t: int, s: int, r1: int, seed: int, instance: int = 0,
+               return_scale: bool = False, row0: int = 0):
+    """Y = Pi1 X for FCT2 (section "FCT2 Construction"), FP64:
+    Pi1 = 8/r1 sqrt(pi t/(2 s)) C Hbar, Hbar block-diagonal with n'/t blocks
+    G = sqrt(t/s) P H_t D (H_t the normalized Sylvester Hadamard of size t, D
+    random signs, P keeping s rows drawn uniformly, with replacement, from t;
+    the paper only asks G to be a fast Johnson-Lindenstrauss matrix, this is
+    the choice), C an r1 x (n' s / t) matrix of independent standard Cauchys.
+    Rows are zero-padded to n' = t ceil(n / t).  ``return_scale`` also
+    returns S_i = max_j 8/r1 sqrt(pi t/(2 s)) sum_m |C_im| sum_v |x_vj| /
+    sqrt(s) (v over the block of m), the magnitude the rounding of any
+    evaluation order is bounded by.  ``row0`` (a multiple of t) places X at
+    global row row0: the streams are indexed by global block and row."""
+    if row0 % t:
+        raise ValueError("row0 must be a multiple of t")
+    X = np.asarray(X, dtype=np.float64)
+    n, q = X.shape
+    n_pad = padded_rows(n, t)
+    nb = n_pad // t
+    z = np.zeros((n_pad, q))
+    z[:n] = X
+    z *= philox.signs(seed, n_pad, instance, row0)[:, None]
+    hz = fwht_blocks(z.reshape(nb, t, q))                 # (nb, t, q), H_t z
+    rows = philox.fct2_rows(seed, nb, s, t, instance, row0 // t)
+    Z = np.sqrt(t / s) * hz[np.arange(nb)[:, None], rows]  # (nb, s, q)
+    Z = Z.reshape(nb * s, q)
+    C = philox.fct2_cauchy(seed, r1, (row0 // t) * s, nb * s, instance)
+    c = fct2_scale(r1, s, t)
+    Y = c * (C @ Z)
+    if not return_scale:
+        return Y
+    absblk = np.abs(z).reshape(nb, t, q).sum(axis=1) / np.sqrt(s)     # (nb, q)
+    zeta = np.repeat(absblk, s, axis=0)                                 # (nb s, q)
+    S = c * (np.abs(C) @ zeta)
+    return Y, S.max(axis=1)
+
+
+def fct2_dense(n: int, t: int, s: int, r1: int, seed: int, instance: int = 0) -> np.ndarray:
+    """Pi1 of FCT2 built entry by entry from its definition (small n)."""
+    n_pad = padded_rows(n, t)
+    nb = n_pad // t
+    D = philox.signs(seed, n_pad, instance)
+    H = hadamard_sylvester(t)  # normalized
+    rows = philox.fct2_rows(seed, nb, s, t, instance)
+    Hbar = np.zeros((nb * s, n_pad))
+    for beta in range(nb):
+        G = np.sqrt(t / s) * H[rows[beta]] * D[beta * t:(beta + 1) * t][None, :]
+        Hbar[beta * s:(beta + 1) * s, beta * t:(beta + 1) * t] = G
+    C = philox.fct2_cauchy(seed, r1, 0, nb * s, instance)
+    return (fct2_scale(r1, s, t) * C @ Hbar)[:, :n]

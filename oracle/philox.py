@@ -32,6 +32,11 @@ written description): key = (seed mod 2^32, seed >> 32); counter =
   (instance k: the k-th of several independent draws from one sampling pass).
 * stream 4, idx = j >> 2: word (j & 3) is the uniform of sample j of a draw
   with replacement (instance k: the k-th draw).
+* stream 5, idx = g >> 2, g = beta s + k: word (g & 3) picks row
+  floor(w t / 2^32) of block beta for sample k of the FCT2 transform's G.
+* stream 6, idx = g >> 2, g = i 2^40 + m: word (g & 3) gives the Cauchy
+  C[i, m] of FCT2's dense r1 x (n s / t) matrix.  FCT2's signs D are
+  stream 1's, like FCT1's.
 
 Pinned by ``tests/test_oracle_rng.py`` against an independent implementation
 (rocRAND's Philox4x32-10 engine, compiled on the host) and by distribution
@@ -52,6 +57,8 @@ STREAM_SIGN = 1
 STREAM_PI2 = 2
 STREAM_SAMPLE = 3
 STREAM_REPLACE = 4
+STREAM_FCT2_ROWS = 5
+STREAM_FCT2_CAUCHY = 6
 
 
 def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
@@ -192,3 +199,23 @@ def replacement_words(seed: int, count: int, instance: int = 0):
     ncalls = (count + 3) >> 2
     words = np.stack(stream_words(seed, STREAM_REPLACE, np.arange(ncalls, dtype=np.uint64), instance), axis=1)
     return words.reshape(-1)[:count]
+
+
+def fct2_rows(seed: int, nblocks: int, s: int, t: int, instance: int = 0, block0: int = 0):
+    """The row of its block (in [0, t)) that FCT2's sample k of block beta
+    takes, for blocks [block0, block0 + nblocks): array (nblocks, s)."""
+    g = (np.arange(block0, block0 + nblocks, dtype=np.uint64)[:, None] * np.uint64(s)
+         + np.arange(s, dtype=np.uint64)[None, :]).reshape(-1)
+    words = np.stack(stream_words(seed, STREAM_FCT2_ROWS, g >> np.uint64(2), instance), axis=1)
+    w = words[np.arange(g.size), (g & np.uint64(3)).astype(np.int64)].astype(np.uint64)
+    return ((w * np.uint64(t)) >> np.uint64(32)).astype(np.int64).reshape(nblocks, s)
+
+
+def fct2_cauchy(seed: int, r1: int, m0: int, count: int, instance: int = 0):
+    """FCT2's C[i, m] for i < r1 and m in [m0, m0 + count): array (r1, count)."""
+    i = np.arange(r1, dtype=np.uint64)[:, None]
+    m = np.arange(m0, m0 + count, dtype=np.uint64)[None, :]
+    g = ((i << np.uint64(40)) | m).reshape(-1)
+    words = np.stack(stream_words(seed, STREAM_FCT2_CAUCHY, g >> np.uint64(2), instance), axis=1)
+    w = words[np.arange(g.size), (g & np.uint64(3)).astype(np.int64)]
+    return cauchy_from_word(w).reshape(r1, count)
