@@ -14,6 +14,9 @@
  *                    gathered coreset (D A, D b) without the weights applied;
  *   l1_regress       steps 1-8: x_hat = argmin ||D A x - D b||_1 (step 8 by
  *                    FP64 iteratively reweighted least squares on the GPU).
+ *   fct2_sketch      Pi1 X with the FCT2 transform (Section "FCT2
+ *                    Construction"), optional R; FCT_FLAG_FCT2 makes
+ *                    l1_regress take its R from it.
  *
  * Conventions shared by every entry point:
  *   - X = [A, -b] has n rows and q = d + 1 columns when b != NULL, else X = A
@@ -68,6 +71,8 @@ enum {
 #define FCT_FLAG_NO_SIGN_FLIP 1u /* Pi1 without the random sign diagonal: the paper's Pi1 exactly */
 #define FCT_FLAG_GAUSSIAN_PI2 4u /* optimized regression: Pi2 of standard Gaussians (figure
                                     OptimizedFastCauchyRegression), see l1_sample_probs_ex */
+#define FCT_FLAG_FCT2 8u /* l1_regress / l1_coreset: R from the FCT2 sketch (fct2_sketch with
+                             t = s, s = s2) instead of FCT1; other entry points reject it */
 #define FCT_FLAG_DETERMINISTIC 2u /* bitwise-reproducible sketch at any r1 (FP32 data, s <= 1024;
                                      FCT_ERR_BAD_ARG for other shapes)                        */
 
@@ -75,7 +80,7 @@ typedef struct {
   int32_t s;      /* FWHT block size: power of two in [2, 4096]                  */
   int32_t r1;     /* rows of Pi1 (sketch rows), q <= r1 <= 65536                 */
   int32_t r2;     /* columns of Pi2, 1 <= r2 <= 32                               */
-  int32_t pad0;
+  int32_t s2;     /* FCT_FLAG_FCT2 only: rows G keeps per block of s, 1 <= s2 <= min(s, 256) */
   int64_t s_out;  /* expected coreset size: the paper's s in step 6 (> 0)        */
   uint64_t seed;  /* key of every random stream                                  */
   uint32_t flags; /* FCT_FLAG_*                                                   */
@@ -131,6 +136,32 @@ int fct_sketch(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda, f
 int fct_sketch_window(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda,
                       fct_dtype dt, const void *b, int32_t s, int32_t r1, uint64_t seed,
                       int64_t row0, uint32_t flags, void *Y);
+
+/*
+ * fct2_sketch: Y = Pi1 X with the FCT2 transform (section "FCT2
+ * Construction", Theorem FCT2): Pi1 = 8/r1 sqrt(pi t / (2 s)) C Hbar, Hbar
+ * block-diagonal with ceil(n / t) copies of the s x t matrix
+ * G = sqrt(t/s) P H_t D, C an r1 x (ceil(n / t) s) matrix of independent
+ * standard Cauchy variates.  The paper only asks G to be a fast
+ * Johnson-Lindenstrauss transform; here G is the subsampled randomized
+ * Hadamard transform: D random signs (the stream FCT1 uses), H_t the
+ * normalized Hadamard matrix of order t, P keeping s of the t rows drawn
+ * uniformly with replacement.  Rows are padded with zeros to
+ * t * ceil(n / t).  Every random entry comes from the seed (Philox streams
+ * 1, 5 and 6), so the call is deterministic and bitwise reproducible.
+ *   A, lda, b, dt  as in fct_sketch (FCT_F32 or FCT_F64; X = [A, -b] when b
+ *         is not NULL, q = d + 1; X = A otherwise, q = d).
+ *   t: power of two in [64, 4096]; s: 1 <= s <= min(t, 256); q <= r1 <= 65536.
+ *   Y: device, r1 x q column-major (ld = r1), of type dt, or NULL.
+ *   R: device, q x q column-major FP64 upper triangular, Pi1 X = Q R, or
+ *      NULL (q <= 88).  Y and R may not both be NULL.
+ *   Scratch: (ceil(n/t) s) x q FP64 for G applied to every block, plus
+ *   partial sums of about 4096 / ceil(r1 / 256) chunks of r1 x q FP64.
+ *   Device conditions as in fct_sketch.
+ */
+int fct2_sketch(fct_ctx *ctx, const void *A, int64_t n, int32_t d, int64_t lda, fct_dtype dt,
+                const void *b, int32_t t, int32_t s, int32_t r1, uint64_t seed, void *Y,
+                double *R);
 
 /*
  * l1_sample_probs: steps 3-6 of the regression figure.
@@ -397,7 +428,7 @@ int fct_lowp_residual(fct_ctx *ctx, const void *A, const void *b, int64_t n, int
                       double *R_res);
 
 /* words: device uint32 [4 * count], the Philox4x32-10 words of calls
- * idx0 .. idx0 + count - 1 of `stream` (0..4) under `seed`, instance 0. */
+ * idx0 .. idx0 + count - 1 of `stream` (0..6) under `seed`, instance 0. */
 int fct_rng_words(fct_ctx *ctx, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                   uint32_t *words);
 

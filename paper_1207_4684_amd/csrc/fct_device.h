@@ -16,7 +16,11 @@
 //   stream 3: idx = i >> 2, word i & 3 -> uniform deciding row i (instance
 //             k: the k-th of several draws from one sampling pass);
 //   stream 4: idx = j >> 2, word j & 3 -> uniform of sample j of a draw with
-//             replacement (instance k: the k-th draw).
+//             replacement (instance k: the k-th draw);
+//   stream 5: idx = g >> 2, g = beta s + k, word g & 3 -> the row of block
+//             beta that sample k of FCT2's G takes;
+//   stream 6: idx = g >> 2, g = i 2^40 + m, word g & 3 -> Cauchy C[i, m] of
+//             FCT2.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,7 +32,9 @@ enum : uint32_t {
   kStreamSign = 1,
   kStreamPi2 = 2,
   kStreamSample = 3,
-  kStreamReplace = 4
+  kStreamReplace = 4,
+  kStreamFct2Rows = 5,
+  kStreamFct2Cauchy = 6
 };
 
 // a ^ b ^ c in one v_bitop3_b32 (truth table 0x96: odd parity of the inputs)

@@ -71,8 +71,38 @@ int pass1_owner_max_cols(int span);
 size_t pass1_owner_lds(int span, int c);
 int pass1_owner_tile_rows();
 hipError_t launch_pass1_owner(const Pass1Args& a, const Pass1Plan& p, bool vec_ok, hipStream_t st);
+// FCT2: the FJLT blocks (fct2_fjlt_kernel) and the Cauchy contraction.
+constexpr int kFct2MaxS = 256;
+struct Fct2Args {
+  const void* A;
+  const void* b;     // NULL when X = A; else X = [A, -b]
+  int64_t lda;
+  int64_t n;
+  int32_t d;
+  int32_t q;
+  int32_t s;         // rows G keeps per block, 1 <= s <= min(t, kFct2MaxS)
+  int32_t log2t;     // block size t = 2^log2t, 6 <= log2t <= 12
+  int64_t nb;        // blocks, ceil(n / t)
+  int64_t row0g;     // global row of local row 0 (a multiple of t)
+  uint64_t seed;
+  uint32_t instance;
+  double* Z;         // (nb s) x zq row-major, G z per block
+  int32_t zq;        // row stride of Z: q rounded up to whole slices
+  int32_t r1;
+  int64_t K;         // nb s, columns of C
+  int64_t kc;        // columns of C per chunk (a multiple of 4)
+  int32_t nchunks;
+  double scale;      // 8 / r1 sqrt(pi t / (2 s))
+  double* partials;  // [nchunks][q][r1]
+};
+// columns per slice of the contraction for q columns (8, 17 or 33)
+int fct2_slice_width(int q);
+hipError_t launch_fct2_fjlt(const Fct2Args& a, bool f64, hipStream_t st);
+hipError_t launch_fct2_cauchy(const Fct2Args& a, bool f64, hipStream_t st);
+// y_f64 < 0: Y has the partials' type; else FP64 (1) or FP32 (0)
 hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
-                                  double* Yd, int* flag, bool f64, hipStream_t st);
+                                  double* Yd, int* flag, bool f64, hipStream_t st,
+                                  int y_f64 = -1);
 hipError_t launch_rng_words(uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                             uint32_t* out, hipStream_t st);
 hipError_t launch_pi1_streams(uint64_t seed, uint32_t r1, int log2s, uint64_t j0, int64_t count,

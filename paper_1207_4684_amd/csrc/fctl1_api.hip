@@ -362,6 +362,95 @@ int run_sketch(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64
   return FCT_OK;
 }
 
+// ---- FCT2 -------------------------------------------------------------------
+
+struct Fct2Plan {
+  int log2t;
+  int64_t nb, K, kc;
+  int nchunks, zq;
+};
+
+Fct2Plan make_fct2_plan(int64_t n, int q, int t, int s, int r1) {
+  Fct2Plan p{};
+  p.log2t = ilog2(t);
+  p.nb = (n + t - 1) / t;
+  p.K = p.nb * s;
+  const int qc = fct2_slice_width(q);
+  p.zq = (q + qc - 1) / qc * qc;
+  // about 4096 workgroups of 256 rows of C, chunks of at least 64 columns
+  const int64_t per = (int64_t)((r1 + 255) / 256) * (p.zq / qc);
+  int64_t nch = (4096 + per - 1) / per;
+  const int64_t most = (p.K + 63) / 64;
+  if (nch > most) nch = most;
+  if (nch < 1) nch = 1;
+  p.kc = ((p.K + nch - 1) / nch + 3) / 4 * 4;
+  p.nchunks = (int)((p.K + p.kc - 1) / p.kc);
+  return p;
+}
+
+template <typename C>
+void carve_fct2(C& cv, const Fct2Plan& p, int q, int r1, bool want_r) {
+  cv.template take<double>((size_t)p.K * p.zq);
+  cv.template take<double>((size_t)p.nchunks * r1 * q);
+  cv.template take<double>((size_t)r1 * q);
+  if (want_r) cv.template take<double>(qr_work_doubles(r1, q));
+}
+
+int check_fct2_args(const fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda,
+                    fct_dtype dt, const void* b, int32_t t, int32_t s, int32_t r1, bool want_r) {
+  int st = check_common(c, A, n, d, lda);
+  if (st) return st;
+  const int q = d + (b ? 1 : 0);
+  if (dt != FCT_F32 && dt != FCT_F64) return FCT_ERR_BAD_ARG;
+  if (!is_pow2(t) || t < 64 || t > 4096) return FCT_ERR_BAD_ARG;
+  if (s < 1 || s > t || s > kFct2MaxS) return FCT_ERR_BAD_ARG;
+  if (r1 < q || r1 > 65536) return FCT_ERR_BAD_ARG;
+  if (want_r && q > 88) return FCT_ERR_BAD_ARG;
+  if ((n + t - 1) / t > 0x7FFFFFFF) return FCT_ERR_BAD_ARG;
+  return FCT_OK;
+}
+
+// Y = Pi1 X with FCT2 (X = [A, -b] when b is given); R of its QR when R != NULL.
+int run_fct2(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64_t lda,
+             fct_dtype dt, const void* b, int32_t t, int32_t s, int32_t r1, uint64_t seed,
+             void* Y, double* R, const Fct2Plan& p) {
+  const int q = d + (b ? 1 : 0);
+  Fct2Args a{};
+  a.A = A;
+  a.b = b;
+  a.lda = lda;
+  a.n = n;
+  a.d = d;
+  a.q = q;
+  a.s = s;
+  a.log2t = p.log2t;
+  a.nb = p.nb;
+  a.row0g = 0;
+  a.seed = seed;
+  a.instance = 0;
+  a.Z = cv.take<double>((size_t)p.K * p.zq);
+  a.zq = p.zq;
+  a.r1 = r1;
+  a.K = p.K;
+  a.kc = p.kc;
+  a.nchunks = p.nchunks;
+  a.scale = 8.0 / r1 * std::sqrt(3.141592653589793 * t / (2.0 * s));
+  a.partials = cv.take<double>((size_t)p.nchunks * r1 * q);
+  double* Yd = cv.take<double>((size_t)r1 * q);
+  const bool f64 = dt == FCT_F64;
+  prof_begin(c, 0);
+  HIP_TRY(launch_fct2_fjlt(a, f64, c->stream));
+  HIP_TRY(launch_fct2_cauchy(a, f64, c->stream));
+  prof_end(c, 0);
+  HIP_TRY(launch_reduce_partials(a.partials, p.nchunks, r1, q, Y, Yd, c->flags + 0, true,
+                                 c->stream, f64 ? 1 : 0));
+  if (R) {
+    double* work = cv.take<double>(qr_work_doubles(r1, q));
+    HIP_TRY(launch_qr(Yd, r1, q, work, R, f64 ? 1e-13 : 1e-5, c->flags + 1, c->stream));
+  }
+  return FCT_OK;
+}
+
 int check_sketch_args(const fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda,
                       fct_dtype dt, const void* b, int32_t s, int32_t r1, bool want_r) {
   int st = check_common(c, A, n, d, lda);
@@ -676,6 +765,21 @@ int fct_sketch_window(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t l
   return run_sketch(c, cv, A, n, d, lda, dt, b, s, r1, seed, flags, Y, nullptr, nullptr, p, row0);
 }
 
+int fct2_sketch(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fct_dtype dt,
+                const void* b, int32_t t, int32_t s, int32_t r1, uint64_t seed, void* Y,
+                double* R) {
+  int st = check_fct2_args(c, A, n, d, lda, dt, b, t, s, r1, R != nullptr);
+  if (st) return st;
+  if (!Y && !R) return FCT_ERR_BAD_ARG;
+  const int q = d + (b ? 1 : 0);
+  const Fct2Plan p = make_fct2_plan(n, q, t, s, r1);
+  Measure m;
+  carve_fct2(m, p, q, r1, R != nullptr);
+  if ((st = ensure_scratch(c, m.off))) return st;
+  Carve cv(c->scratch);
+  return run_fct2(c, cv, A, n, d, lda, dt, b, t, s, r1, seed, Y, R, p);
+}
+
 int l1_sample_probs_ex(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d,
                        int64_t lda, fct_dtype dt, const double* R, int32_t r2, uint64_t seed,
                        int64_t s_out, uint32_t flags, float* lambda, float* p, double* sum_lambda) {
@@ -757,9 +861,11 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
                         double* w, int64_t* idx, int64_t* S_dev, Carve& cv,
                         const CoresetOut* out = nullptr) {
   const int q = d + 1;
+  const bool fct2 = (prm->flags & FCT_FLAG_FCT2) != 0;
   const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);
+  const Pass1Plan p =
+      fct2 ? Pass1Plan{} : make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   double* R = cv.take<double>((size_t)q * q);
   float* lam = cv.take<float>((size_t)n);
@@ -768,9 +874,13 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
   {
     Carve sub(cv.base);
     sub.off = cv.off;
-    if ((st = run_sketch(c, sub, A, n, d, lda, dt, b, prm->s, prm->r1, prm->seed, prm->flags,
-                         nullptr, R, nullptr, p)))
-      return st;
+    if (fct2)
+      st = run_fct2(c, sub, A, n, d, lda, dt, b, prm->s, prm->s2, prm->r1, prm->seed, nullptr, R,
+                    make_fct2_plan(n, q, prm->s, prm->s2, prm->r1));
+    else
+      st = run_sketch(c, sub, A, n, d, lda, dt, b, prm->s, prm->r1, prm->seed, prm->flags,
+                      nullptr, R, nullptr, p);
+    if (st) return st;
   }
   {
     Carve sub(cv.base);
@@ -802,16 +912,22 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
 static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype dt,
                               const fct_params* prm, bool lowp) {
   const int q = d + 1;
+  const bool fct2 = (prm->flags & FCT_FLAG_FCT2) != 0;
   const int64_t n_pad = (n + prm->s - 1) / prm->s * prm->s;
   int perr = 0;
-  const Pass1Plan p = make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);
   Measure m;
   m.take<double>((size_t)q * q);
   m.take<float>((size_t)n);
   m.take<double>(1);
   const size_t base = m.off;
   Measure a, bb, cc;
-  carve_sketch(a, p, n_pad, q, prm->r1, esize(dt), true);
+  if (fct2) {
+    carve_fct2(a, make_fct2_plan(n, q, prm->s, prm->s2, prm->r1), q, prm->r1, true);
+  } else {
+    const Pass1Plan p =
+        make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);
+    carve_sketch(a, p, n_pad, q, prm->r1, esize(dt), true);
+  }
   carve_probs(bb, c, q, prm->r2, n, lowp ? kPass2BF16 : (dt == FCT_F64 ? kPass2F64 : kPass2F32));
   carve_select(cc, n);
   size_t mx = a.off;
@@ -820,9 +936,14 @@ static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype 
   return base + mx + 1024;
 }
 
-static int check_params(const fct_params* prm, int q) {
+// FCT_FLAG_FCT2 is taken by l1_regress and l1_coreset only (allow_fct2).
+static int check_params(const fct_params* prm, int q, bool allow_fct2 = false) {
   if (!prm) return FCT_ERR_BAD_ARG;
   if (!is_pow2(prm->s) || prm->s < 2 || prm->s > 4096) return FCT_ERR_BAD_ARG;
+  if (prm->flags & FCT_FLAG_FCT2) {
+    if (!allow_fct2 || prm->s < 64 || prm->s2 < 1 || prm->s2 > prm->s || prm->s2 > kFct2MaxS)
+      return FCT_ERR_BAD_ARG;
+  }
   if (prm->r1 < q || prm->r1 > 65536 || prm->r2 < 1 || prm->r2 > 32) return FCT_ERR_BAD_ARG;
   if (q > 65) return FCT_ERR_BAD_ARG;  // solver and panel QR limits: d <= 64
   return FCT_OK;
@@ -835,7 +956,7 @@ int l1_coreset(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, i
   int st = check_common(c, A, n, d, lda);
   if (st) return st;
   if (!b || (dt != FCT_F32 && dt != FCT_F64)) return FCT_ERR_BAD_ARG;
-  if ((st = check_params(prm, d + 1))) return st;
+  if ((st = check_params(prm, d + 1, true))) return st;
   if (prm->s_out < 1 || cap < 1 || !At || !bt || !w || !idx || !S) return FCT_ERR_BAD_ARG;
   if (A_lowp && (!b_lowp || ld_lowp < n)) return FCT_ERR_BAD_ARG;
   const size_t need = coreset_scratch(c, n, d, dt, prm, A_lowp != nullptr) + 256;
@@ -946,7 +1067,7 @@ int l1_regress(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, i
     if (!(eps > 0.0)) return FCT_ERR_BAD_ARG;
     prm.s_out = (int64_t)std::ceil(20.0 * (d + 1) / eps);
   }
-  if ((st = check_params(&prm, d + 1))) return st;
+  if ((st = check_params(&prm, d + 1, true))) return st;
   if (A_lowp && (!b_lowp || ld_lowp < n)) return FCT_ERR_BAD_ARG;
   const int iters = prm.irls_iters > 0 ? prm.irls_iters : 80;
   int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
@@ -1735,7 +1856,7 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
 
 int fct_rng_words(fct_ctx* c, uint32_t stream, uint64_t seed, uint64_t idx0, int64_t count,
                   uint32_t* words) {
-  if (!c || !words || count < 0 || stream > 4) return FCT_ERR_BAD_ARG;
+  if (!c || !words || count < 0 || stream > 6) return FCT_ERR_BAD_ARG;
   if (count == 0) return FCT_OK;
   HIP_TRY(launch_rng_words(stream, seed, idx0, count, words, c->stream));
   return FCT_OK;

@@ -180,10 +180,10 @@ __global__ void __launch_bounds__(1024) pass1_kernel(Pass1Args a) {
 // wave order.
 constexpr int kRedGroups = 8;
 
-template <typename T>
+template <typename T, typename TY>
 __global__ void __launch_bounds__(64 * kRedGroups)
 reduce_partials_kernel(const T* __restrict__ part, int nranges, int r1, int q,
-                       T* __restrict__ Y, double* __restrict__ Yd, int* __restrict__ flag) {
+                       TY* __restrict__ Y, double* __restrict__ Yd, int* __restrict__ flag) {
   __shared__ double ws[kRedGroups][64];
   const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * 64 + i;
@@ -198,7 +198,7 @@ reduce_partials_kernel(const T* __restrict__ part, int nranges, int r1, int q,
 #pragma unroll
   for (int k = 1; k < kRedGroups; ++k) s += ws[k][i];
   if (Yd) Yd[idx] = s;
-  if (Y) Y[idx] = (T)s;
+  if (Y) Y[idx] = (TY)s;
   if (!isfinite(s)) *flag = 1;
 }
 
@@ -230,16 +230,22 @@ hipError_t launch_pass1(const Pass1Args& a, const Pass1Plan& p, bool f64, hipStr
 }
 
 hipError_t launch_reduce_partials(const void* part, int nranges, int r1, int q, void* Y,
-                                  double* Yd, int* flag, bool f64, hipStream_t st) {
+                                  double* Yd, int* flag, bool f64, hipStream_t st, int y_f64) {
   const int64_t tot = (int64_t)r1 * q;
   const int threads = 64 * kRedGroups;
   const int blocks = (int)((tot + 63) / 64);
-  if (f64)
-    hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(blocks), dim3(threads), 0, st,
-                       (const double*)part, nranges, r1, q, (double*)Y, Yd, flag);
+  const bool yd = y_f64 < 0 ? f64 : y_f64 != 0;
+  if (f64 && yd)
+    hipLaunchKernelGGL((reduce_partials_kernel<double, double>), dim3(blocks), dim3(threads), 0,
+                       st, (const double*)part, nranges, r1, q, (double*)Y, Yd, flag);
+  else if (f64)
+    hipLaunchKernelGGL((reduce_partials_kernel<double, float>), dim3(blocks), dim3(threads), 0,
+                       st, (const double*)part, nranges, r1, q, (float*)Y, Yd, flag);
+  else if (!yd)
+    hipLaunchKernelGGL((reduce_partials_kernel<float, float>), dim3(blocks), dim3(threads), 0,
+                       st, (const float*)part, nranges, r1, q, (float*)Y, Yd, flag);
   else
-    hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(blocks), dim3(threads), 0, st,
-                       (const float*)part, nranges, r1, q, (float*)Y, Yd, flag);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ FCT_SAMPLE_BERNOULLI, FCT_SAMPLE_REPLACE = 0, 1
 FCT_FLAG_NO_SIGN_FLIP = 1
 FCT_FLAG_DETERMINISTIC = 2
 FCT_FLAG_GAUSSIAN_PI2 = 4
+FCT_FLAG_FCT2 = 8
 FCT_OPT_PASS1_KERNEL, FCT_OPT_PASS1_WGS_PER_CU, FCT_OPT_PASS1_TILE_THREADS = 1, 2, 3
 FCT_OPT_PASS2_WGS, FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS = 4, 5, 6
 FCT_P1_AUTO, FCT_P1_WAVE, FCT_P1_OWNER, FCT_P1_TILE = 0, 1, 2, 3
@@ -37,7 +38,7 @@ class FctError(RuntimeError):
 
 class fct_params(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("s_out", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("s2", ctypes.c_int32), ("s_out", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32), ("irls_iters", ctypes.c_int32)]
 
 
@@ -66,6 +67,7 @@ def _load():
         "fct_sketch": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, P, I32, I32, U64, U32, P, P]),
         "fct_sketch_window": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, P, I32, I32, U64,
                                              I64, U32, P]),
+        "fct2_sketch": (ctypes.c_int, [P, P, I64, I32, I64, ctypes.c_int, P, I32, I32, I32, U64, P, P]),
         "l1_sample_probs": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64, I64,
                                            P, P, P]),
         "l1_sample_probs_ex": (ctypes.c_int, [P, P, P, I64, I32, I64, ctypes.c_int, P, I32, U64,
@@ -117,7 +119,7 @@ EXPORTED = ("fct_create", "fct_destroy", "fct_strerror", "fct_sync", "fct_stream
             "fct_to_bf16", "fct_lowp_residual", "fct_l1_objective", "l1_solve", "l1_select",
             "fct_profile", "fct_profile_read", "l1_regress_batched", "fct_set_option",
             "l1_select_draw", "l1_regress_multi", "l1_regress_mrhs", "l1_subspace",
-            "fct_l1_objectives")
+            "fct_l1_objectives", "fct2_sketch")
 
 
 def _check(st: int, where: str):
@@ -219,8 +221,9 @@ class Context:
         return ms.value, cnt.value
 
 
-def params(s, r1, r2, s_out, seed, flags=0, irls_iters=0):
-    return fct_params(s=s, r1=r1, r2=r2, pad0=0, s_out=int(s_out), seed=seed, flags=flags,
+def params(s, r1, r2, s_out, seed, flags=0, irls_iters=0, s2=0):
+    """fct_params; with FCT_FLAG_FCT2, s is FCT2's block size t and s2 its s."""
+    return fct_params(s=s, r1=r1, r2=r2, s2=s2, s_out=int(s_out), seed=seed, flags=flags,
                       irls_iters=irls_iters)
 
 
@@ -232,6 +235,17 @@ def fct_sketch(ctx, A, b, s, r1, seed, flags=0, want_y=True, want_r=True):
     R = torch.empty((q, q), dtype=torch.float64, device=A.device) if want_r else None
     _check(ctx.call(_lib.fct_sketch, ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), s, r1, seed, flags,
                            _ptr(Y), _ptr(R)), "fct_sketch")
+    return (Y.t() if Y is not None else None), (R.t() if R is not None else None)
+
+
+def fct2_sketch(ctx, A, b, t, s, r1, seed, want_y=True, want_r=True):
+    """Y = Pi1 X with FCT2 (r1 x q view) and R (q x q view, FP64)."""
+    n, d, lda = _cm(A)
+    q = d + (1 if b is not None else 0)
+    Y = torch.empty((q, r1), dtype=A.dtype, device=A.device) if want_y else None
+    R = torch.empty((q, q), dtype=torch.float64, device=A.device) if want_r else None
+    _check(ctx.call(_lib.fct2_sketch, ctx.handle, _ptr(A), n, d, lda, _dt(A), _ptr(b), t, s, r1, seed,
+                    _ptr(Y), _ptr(R)), "fct2_sketch")
     return (Y.t() if Y is not None else None), (R.t() if R is not None else None)
 
 

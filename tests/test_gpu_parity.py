@@ -44,7 +44,7 @@ def host(t):
 
 # ---- random streams --------------------------------------------------------
 
-@pytest.mark.parametrize("stream", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("stream", [0, 1, 2, 3, 4, 5, 6])
 def test_rng_words_bit_exact(F, ctx, stream):
     for idx0 in (0, 2**32 - 5, 2**40 + 3):
         seed = 0x123456789ABCDEF + stream
