@@ -35,6 +35,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Π1A + sampling pass GB/s (% HBM peak); ℓ1 solve time at (1+ε) opt, plain vs BF16"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
+# second (one wave64 VALU instruction takes 4 cycles of a 16-lane SIMD)
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# VALU instructions per C entry of the FCT2 contraction's inner loop (the
+# 17-column slice compiled for gfx950: 244 per Philox call of 4 entries, 68 of
+# them FP64 FMAs): 44 to draw and transform the variate plus one FMA per column
+FCT2_GEN_VALU_PER_ENTRY = 44
 CHUNK = 1 << 20
 
 
@@ -231,7 +238,7 @@ def jaccard(a, b):
 
 
 def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, err_report=False,
-                 multi=0):
+                 multi=0, fct2=None):
     """Time l1_regress on workload w (plain and, for FP32 data, the BF16
     sampling pass); pass times from the library's events; objectives from the
     library (fct_l1_objective) against an all-rows solve by the library."""
@@ -330,6 +337,9 @@ def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, er
         rec["multi"] = m
         progress(f"{w.name}: {multi} draws per pass: bernoulli {m['bernoulli_ms']} ms, "
                  f"replace {m['replace_ms']} ms")
+    x_fct2 = None
+    if fct2 is not None and not f64:
+        rec["fct2"], x_fct2 = bench_fct2(F, torch, ctx, w, Ad, bd, flush, **fct2)
     if ref:
         x_ref, _ = F.l1_solve(ctx, Ad, bd, torch.ones(w.n, dtype=torch.float64, device="cuda"),
                               iters=120)
@@ -341,9 +351,49 @@ def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, er
         for name, X in xs_multi.items():
             rec["multi"][f"{name}_ratio_max"] = max(
                 F.fct_l1_objective(ctx, Ad, bd, X[k]) / f_ref for k in range(X.shape[0]))
+        if x_fct2 is not None:
+            rec["fct2"]["regress_ratio"] = F.fct_l1_objective(ctx, Ad, bd, x_fct2) / f_ref
     del Ad, bd
     torch.cuda.empty_cache()
     return rec
+
+
+def bench_fct2(F, torch, ctx, w, Ad, bd, flush, t=4096, s=32, steps=5):
+    """The FCT2 sketch Pi1 [A, -b] (block size t, s sampled rows per block,
+    r1 of the workload) and the regression that takes its R from it.  Kernel
+    times from the library's events: the FJLT blocks read X once and write
+    G z (HBM); the contraction generates r1 x (n s / t) Cauchy variates
+    (VALU)."""
+    q = w.d + 1
+    nb = -(-w.n // t)
+    K = nb * s
+    qc = 8 if q <= 8 else 17 if q <= 17 else 33
+    zq = -(-q // qc) * qc
+    valu_per_entry = (zq // qc) * FCT2_GEN_VALU_PER_ENTRY + zq
+    ctx.profile(True)
+    times, _ = timed_steps(torch, lambda: F.fct2_sketch(ctx, Ad, bd, t, s, w.r1, w.seed, want_y=False),
+                           steps, 1, flush)
+    fj = ctx.profile_read(3)
+    ca = ctx.profile_read(4)
+    ctx.profile(False)
+    fj_ms = fj[0] / max(1, fj[1])
+    ca_ms = ca[0] / max(1, ca[1])
+    fj_bytes = w.n * q * 4 + K * zq * 8
+    entries = w.r1 * K
+    out = {"t": t, "s": s, "r1": w.r1, "sketch_ms": round(statistics.median(times) * 1e3, 4),
+           "fjlt_ms": round(fj_ms, 5), "fjlt_algorithmic_bytes": fj_bytes,
+           "fjlt_GBps": round(fj_bytes / (fj_ms * 1e-3) / 1e9, 1),
+           "fjlt_frac": round(fj_bytes / (fj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "contraction_ms": round(ca_ms, 5), "cauchy_entries": entries,
+           "cauchy_entries_per_s": round(entries / (ca_ms * 1e-3)),
+           "contraction_valu_lane_ops_per_entry": valu_per_entry,
+           "contraction_valu_frac": round(entries * valu_per_entry / (ca_ms * 1e-3) / VALU_PEAK_LANE_OPS, 4)}
+    prm = F.params(s=t, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed, flags=F.FCT_FLAG_FCT2, s2=s)
+    tr, res = timed_steps(torch, lambda: F.l1_regress(ctx, Ad, bd, prm, eps=w.eps), 3, 1, flush)
+    out.update({"regress_ms": round(statistics.median(tr) * 1e3, 4), "regress_coreset_rows": int(res[2])})
+    progress(f"{w.name}: FCT2 sketch {out['sketch_ms']} ms (FJLT {out['fjlt_ms']} ms, "
+             f"contraction {out['contraction_ms']} ms), regression {out['regress_ms']} ms")
+    return out, res[0]
 
 
 def bf16_error_report(F, torch, ctx, w, Ad, bd, Al, bl):
@@ -515,6 +565,9 @@ def main():
                     help="skip the multiple-regression and subspace timings")
     ap.add_argument("--multi", type=int, default=16,
                     help="coresets per sampling pass timed on the headline workload (0 = skip)")
+    ap.add_argument("--fct2-t", type=int, default=4096,
+                    help="FCT2 block size timed on the headline workload (0 = skip)")
+    ap.add_argument("--fct2-s", type=int, default=32, help="FCT2 rows sampled per block")
     ap.add_argument("--cpu-rows", type=int, default=1 << 26, help="rows of the CPU baseline's sample")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solves")
@@ -537,7 +590,8 @@ def main():
     ctx = F.Context(0)
     flush = Flusher(torch)
     head = run_workload(F, torch, ctx, w, args.steps, args.warmup, flush, ref=not args.skip_ref,
-                        err_report=w.dtype == "f32", multi=args.multi)
+                        err_report=w.dtype == "f32", multi=args.multi,
+                        fct2=dict(t=args.fct2_t, s=args.fct2_s) if args.fct2_t > 0 else None)
     if args.profile_copy_mib > 0:
         src = torch.empty(args.profile_copy_mib << 18, dtype=torch.float32, device="cuda")
         src.fill_(1.0)

@@ -447,8 +447,9 @@ int fct_pi1_streams(fct_ctx *ctx, uint64_t seed, int32_t r1, int32_t s, uint64_t
 int fct_fwht(fct_ctx *ctx, float *x, int64_t nblocks, int32_t s);
 
 /* Kernel timing: enable != 0 starts recording HIP events around every
- * pass-1 kernel (kind 0), pass-2 kernel (kind 1) and step-8 solve sequence
- * (kind 2) launched on the context's stream (up to 512 of each; counts are
+ * pass-1 kernel (kind 0), pass-2 kernel (kind 1), step-8 solve sequence
+ * (kind 2), FCT2 FJLT kernel (kind 3) and FCT2 Cauchy contraction (kind 4)
+ * launched on the context's stream (up to 512 of each; counts are
  * reset); 0 stops.  fct_profile_read waits for the stream and returns the
  * summed device milliseconds and the number of launches of `kind`. */
 int fct_profile(fct_ctx *ctx, int enable);

@@ -147,7 +147,7 @@ def fct2_scale(r1: int, s: int, t: int) -> float:
 
 
 def fct2_apply(X, t: int, s: int, r1: int, seed: int, instance: int = 0,
-               return_scale: bool = False, row0: int = 0):
+               return_scale: bool = False, row0: int = 0, scale_per_column: bool = False):
     """Y = Pi1 X for FCT2 (section "FCT2 Construction"), FP64:
     Pi1 = 8/r1 sqrt(pi t/(2 s)) C Hbar, Hbar block-diagonal with n'/t blocks
     G = sqrt(t/s) P H_t D (H_t the normalized Sylvester Hadamard of size t, D
@@ -157,8 +157,10 @@ def fct2_apply(X, t: int, s: int, r1: int, seed: int, instance: int = 0,
     Rows are zero-padded to n' = t ceil(n / t).  ``return_scale`` also
     returns S_i = max_j 8/r1 sqrt(pi t/(2 s)) sum_m |C_im| sum_v |x_vj| /
     sqrt(s) (v over the block of m), the magnitude the rounding of any
-    evaluation order is bounded by.  ``row0`` (a multiple of t) places X at
-    global row row0: the streams are indexed by global block and row."""
+    evaluation order is bounded by (``scale_per_column``: the (r1, q) masses
+    before the max, which add up over row windows).  ``row0`` (a multiple of
+    t) places X at global row row0: the streams are indexed by global block
+    and row."""
     if row0 % t:
         raise ValueError("row0 must be a multiple of t")
     X = np.asarray(X, dtype=np.float64)
@@ -180,7 +182,7 @@ def fct2_apply(X, t: int, s: int, r1: int, seed: int, instance: int = 0,
     absblk = np.abs(z).reshape(nb, t, q).sum(axis=1) / np.sqrt(s)     # (nb, q)
     zeta = np.repeat(absblk, s, axis=0)                                 # (nb s, q)
     S = c * (np.abs(C) @ zeta)
-    return Y, S.max(axis=1)
+    return Y, (S if scale_per_column else S.max(axis=1))
 
 
 def fct2_dense(n: int, t: int, s: int, r1: int, seed: int, instance: int = 0) -> np.ndarray:

@@ -18,9 +18,10 @@
 //    row-major (n' s / t) x zq.  Streams X once: HBM-bound.
 //  * fct2_cauchy_kernel -- the dense contraction Y = c C Z.  A thread owns
 //    one row i of C and a chunk of m; C is never stored (one Philox call
-//    gives C[i, m .. m + 3]); rows of Z are wave-uniform scalar loads; FP64
-//    accumulators.  Per-chunk partials are reduced in a fixed order by
-//    launch_reduce_partials.  Bound by the generation of C (VALU).
+//    gives C[i, m .. m + 3]); tiles of Z rows are staged in LDS and read as
+//    wave-uniform broadcasts; FP64 accumulators.  Per-chunk partials are
+//    reduced in a fixed order by launch_reduce_partials.  Bound by the
+//    generation of C (VALU).
 #include "fct_device.h"
 #include "fct_kernels.h"
 
@@ -135,6 +136,8 @@ template <> __device__ __forceinline__ double fct2_cauchy<double>(uint32_t w) {
 
 template <typename TC, int QC>
 __global__ void __launch_bounds__(256) fct2_cauchy_kernel(Fct2Args a) {
+  constexpr int MT = 64;  // rows of Z per LDS tile
+  __shared__ double zt[MT * QC];
   const int i = blockIdx.y * 256 + threadIdx.x;
   const int64_t m0 = (int64_t)blockIdx.x * a.kc;
   const int64_t m1 = min(a.K, m0 + a.kc);
@@ -143,17 +146,26 @@ __global__ void __launch_bounds__(256) fct2_cauchy_kernel(Fct2Args a) {
   double acc[QC];
 #pragma unroll
   for (int jj = 0; jj < QC; ++jj) acc[jj] = 0.0;
-  for (int64_t m = m0; m < m1; m += 4) {
-    const uint4 w = stream_words(a.seed, kStreamFct2Cauchy, ihi | (uint64_t)(m >> 2), a.instance);
-    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+  for (int64_t mt = m0; mt < m1; mt += MT) {
+    const int rows = (int)min((int64_t)MT, m1 - mt);
+    __syncthreads();  // the previous tile's reads are done
+    for (int e = threadIdx.x; e < rows * QC; e += 256) {
+      const int r = e / QC, jj = e - r * QC;
+      zt[e] = zs[(size_t)(mt + r) * a.zq + jj];
+    }
+    __syncthreads();
+    for (int r = 0; r < rows; r += 4) {  // mt and r are multiples of 4
+      const uint4 w =
+          stream_words(a.seed, kStreamFct2Cauchy, ihi | (uint64_t)((mt + r) >> 2), a.instance);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t mu = m + u;
-      const bool in = mu < m1;
-      const double cv = in ? fct2_cauchy<TC>(ws[u]) : 0.0;
-      const double* __restrict__ zr = zs + (size_t)(in ? mu : m0) * a.zq;
+      for (int u = 0; u < 4; ++u) {
+        const bool in = r + u < rows;
+        const double cv = in ? fct2_cauchy<TC>(ws[u]) : 0.0;
+        const double* z = zt + (in ? r + u : 0) * QC;  // wave-uniform: LDS broadcast
 #pragma unroll
-      for (int jj = 0; jj < QC; ++jj) acc[jj] = fma(cv, zr[jj], acc[jj]);
+        for (int jj = 0; jj < QC; ++jj) acc[jj] = fma(cv, z[jj], acc[jj]);
+      }
     }
   }
   if (i >= a.r1) return;

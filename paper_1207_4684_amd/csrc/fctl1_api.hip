@@ -42,9 +42,10 @@ struct fct_ctx {
   size_t lds_optin = 65536;
   // optional per-kernel timing with HIP events on the context stream
   static constexpr int kProfSlots = 512;
+  static constexpr int kProfKinds = 5;
   bool prof_on = false;
-  int prof_n[3] = {0, 0, 0};
-  hipEvent_t* prof_ev[3] = {nullptr, nullptr, nullptr};  // pairs (start, stop)
+  int prof_n[kProfKinds] = {};
+  hipEvent_t* prof_ev[kProfKinds] = {};  // pairs (start, stop)
   // plan knobs (fct_set_option)
   int p1_kernel = FCT_P1_AUTO;  // pass-1 kernel choice
   int p1_threads = 256;         // workgroup-tile kernel threads
@@ -66,7 +67,8 @@ struct fct_ctx {
 
 namespace {
 
-// timing brackets around one launch sequence of kind k (0 pass 1, 1 pass 2, 2 solve)
+// timing brackets around one launch sequence of kind k (0 pass 1, 1 pass 2, 2 solve,
+// 3 FCT2 FJLT blocks, 4 FCT2 Cauchy contraction)
 void prof_begin(fct_ctx* c, int k) {
   if (!c->prof_on || !c->prof_ev[k] || c->prof_n[k] >= fct_ctx::kProfSlots) return;
   (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k]], c->stream);
@@ -438,10 +440,12 @@ int run_fct2(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64_t
   a.partials = cv.take<double>((size_t)p.nchunks * r1 * q);
   double* Yd = cv.take<double>((size_t)r1 * q);
   const bool f64 = dt == FCT_F64;
-  prof_begin(c, 0);
+  prof_begin(c, 3);
   HIP_TRY(launch_fct2_fjlt(a, f64, c->stream));
+  prof_end(c, 3);
+  prof_begin(c, 4);
   HIP_TRY(launch_fct2_cauchy(a, f64, c->stream));
-  prof_end(c, 0);
+  prof_end(c, 4);
   HIP_TRY(launch_reduce_partials(a.partials, p.nchunks, r1, q, Y, Yd, c->flags + 0, true,
                                  c->stream, f64 ? 1 : 0));
   if (R) {
@@ -628,7 +632,7 @@ int fct_create(fct_ctx** out, int device, void* hip_stream) {
 void fct_destroy(fct_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < fct_ctx::kProfKinds; ++k) {
     if (!c->prof_ev[k]) continue;
     for (int i = 0; i < 2 * fct_ctx::kProfSlots; ++i) (void)hipEventDestroy(c->prof_ev[k][i]);
     delete[] c->prof_ev[k];
@@ -702,7 +706,7 @@ int fct_set_option(fct_ctx* c, int option, int64_t value) {
 int fct_profile(fct_ctx* c, int enable) {
   if (!c) return FCT_ERR_BAD_ARG;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < fct_ctx::kProfKinds; ++k) {
     c->prof_n[k] = 0;
     if (enable && !c->prof_ev[k]) {
       c->prof_ev[k] = new (std::nothrow) hipEvent_t[2 * fct_ctx::kProfSlots];
@@ -716,7 +720,7 @@ int fct_profile(fct_ctx* c, int enable) {
 }
 
 int fct_profile_read(fct_ctx* c, int kind, double* total_ms, int64_t* count) {
-  if (!c || kind < 0 || kind > 2 || !total_ms || !count) return FCT_ERR_BAD_ARG;
+  if (!c || kind < 0 || kind >= fct_ctx::kProfKinds || !total_ms || !count) return FCT_ERR_BAD_ARG;
   HIP_TRY(hipStreamSynchronize(c->stream));
   double tot = 0.0;
   for (int i = 0; i < c->prof_n[kind]; ++i) {
