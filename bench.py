@@ -370,17 +370,25 @@ def bench_fct2(F, torch, ctx, w, Ad, bd, flush, t=4096, s=32, steps=5):
     qc = 8 if q <= 8 else 17 if q <= 17 else 33
     zq = -(-q // qc) * qc
     valu_per_entry = (zq // qc) * FCT2_GEN_VALU_PER_ENTRY + zq
+    def sketch():
+        return F.fct2_sketch(ctx, Ad, bd, t, s, w.r1, w.seed, want_y=False)
+    # the default launch (each kernel alone on the device: per-kernel
+    # rooflines), then the option that runs the contraction of one segment
+    # beside the FJLT of the next
     ctx.profile(True)
-    times, _ = timed_steps(torch, lambda: F.fct2_sketch(ctx, Ad, bd, t, s, w.r1, w.seed, want_y=False),
-                           steps, 1, flush)
+    times, _ = timed_steps(torch, sketch, steps, 1, flush)
     fj = ctx.profile_read(3)
     ca = ctx.profile_read(4)
     ctx.profile(False)
+    ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 1)
+    t_ov, _ = timed_steps(torch, sketch, steps, 1, flush)
+    ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 0)
     fj_ms = fj[0] / max(1, fj[1])
     ca_ms = ca[0] / max(1, ca[1])
     fj_bytes = w.n * q * 4 + K * zq * 8
     entries = w.r1 * K
     out = {"t": t, "s": s, "r1": w.r1, "sketch_ms": round(statistics.median(times) * 1e3, 4),
+           "sketch_overlap_option_ms": round(statistics.median(t_ov) * 1e3, 4),
            "fjlt_ms": round(fj_ms, 5), "fjlt_algorithmic_bytes": fj_bytes,
            "fjlt_GBps": round(fj_bytes / (fj_ms * 1e-3) / 1e9, 1),
            "fjlt_frac": round(fj_bytes / (fj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

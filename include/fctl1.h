@@ -464,14 +464,21 @@ int fct_profile_read(fct_ctx *ctx, int kind, double *total_ms, int64_t *count);
  * FCT_OPT_PASS1_TILE_THREADS: 256, 512 or 1024.  FCT_OPT_PASS2_WGS: cap of the
  * FP32/BF16 pass-2 grid (0 = default).  FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS:
  * workgroups of the coreset solve, or coreset rows per workgroup (0 =
- * default).  Returns FCT_ERR_BAD_ARG for an unknown option or value. */
+ * default).  FCT_OPT_FCT2_OVERLAP: 1 runs FCT2's Cauchy contraction of each
+ * eighth of the rows on a second stream while a capped FJLT grid works on
+ * the next eighth (measured slower than the default on MI355X: the two
+ * kernels contend for the same CUs); 0 (default) runs the two kernels one
+ * after the other, each over all rows.  Returns
+ * FCT_ERR_BAD_ARG for an unknown option or value.
+ */
 enum {
   FCT_OPT_PASS1_KERNEL = 1,
   FCT_OPT_PASS1_WGS_PER_CU = 2,
   FCT_OPT_PASS1_TILE_THREADS = 3,
   FCT_OPT_PASS2_WGS = 4,
   FCT_OPT_SOLVE_WGS = 5,
-  FCT_OPT_SOLVE_ROWS = 6
+  FCT_OPT_SOLVE_ROWS = 6,
+  FCT_OPT_FCT2_OVERLAP = 7
 };
 enum { FCT_P1_AUTO = 0, FCT_P1_WAVE = 1, FCT_P1_OWNER = 2, FCT_P1_TILE = 3 };
 int fct_set_option(fct_ctx *ctx, int option, int64_t value);

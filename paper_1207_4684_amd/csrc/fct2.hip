@@ -37,93 +37,98 @@ __global__ void __launch_bounds__(64) fct2_fjlt_kernel(Fct2Args a) {
   __shared__ uint32_t sw[TT / 32];
   __shared__ int32_t rows[kFct2MaxS];
   const int l = threadIdx.x;
-  const int64_t beta = blockIdx.x;
-  const int64_t r0 = beta * TT;
-  const uint64_t g0 = (uint64_t)(a.row0g + r0);
+  // blocks beta0 + blockIdx.x, + gridDim.x, ... (the grid may be capped to leave
+  // room for a concurrent contraction)
+  for (int64_t bb = blockIdx.x; bb < a.nbl; bb += gridDim.x) {
+    __syncthreads();  // the previous block's reads of sw and rows are done
+    const int64_t beta = a.beta0 + bb;
+    const int64_t r0 = beta * TT;
+    const uint64_t g0 = (uint64_t)(a.row0g + r0);
 
-  // sign words of the block's rows (stream 1: bit j & 31 of word (j >> 5) & 3
-  // of call j >> 7) and the s sampled rows (stream 5)
-  for (int k = l; k < TT / 32; k += 64) {
-    const uint64_t j = g0 + 32ull * (uint64_t)k;
-    const uint4 w = stream_words(a.seed, kStreamSign, j >> 7, a.instance);
-    const uint32_t sel = (uint32_t)(j >> 5) & 3u;
-    sw[k] = sel == 0 ? w.x : sel == 1 ? w.y : sel == 2 ? w.z : w.w;
-  }
-  const uint64_t gbeta = (uint64_t)(a.row0g / TT + beta);
-  for (int k = l; k < a.s; k += 64) {
-    const uint64_t g = gbeta * (uint64_t)a.s + (uint64_t)k;
-    const uint4 w = stream_words(a.seed, kStreamFct2Rows, g >> 2, a.instance);
-    const uint32_t sel = (uint32_t)g & 3u;
-    const uint32_t wd = sel == 0 ? w.x : sel == 1 ? w.y : sel == 2 ? w.z : w.w;
-    rows[k] = (int32_t)(wd >> (32 - LOG2T));  // floor(w t / 2^32)
-  }
-  __syncthreads();
-  // bit m: D is -1 at element m * 64 + l
-  uint64_t smask = 0;
-#pragma unroll
-  for (int m = 0; m < P; ++m)
-    smask |= (uint64_t)((sw[2 * m + (l >> 5)] >> (l & 31)) & 1u) << m;
-
-  const int mm = l / PAD, ll = l % PAD;  // transposed role of this lane
-  const double zscale = 1.0 / sqrt((double)a.s);
-  for (int j = 0; j < a.q; ++j) {
-    const bool negcol = j >= a.d;  // X = [A, -b]
-    const T* col = negcol ? (const T*)a.b : (const T*)a.A + (size_t)j * a.lda;
-    T v[P];
-#pragma unroll
-    for (int m = 0; m < P; ++m) {
-      const int64_t row = r0 + m * 64 + l;
-      const T x = row < a.n ? col[row] : T(0);
-      v[m] = (((smask >> m) & 1) != 0) != negcol ? -x : x;
+    // sign words of the block's rows (stream 1: bit j & 31 of word (j >> 5) & 3
+    // of call j >> 7) and the s sampled rows (stream 5)
+    for (int k = l; k < TT / 32; k += 64) {
+      const uint64_t j = g0 + 32ull * (uint64_t)k;
+      const uint4 w = stream_words(a.seed, kStreamSign, j >> 7, a.instance);
+      const uint32_t sel = (uint32_t)(j >> 5) & 3u;
+      sw[k] = sel == 0 ? w.x : sel == 1 ? w.y : sel == 2 ? w.z : w.w;
     }
-    // element bits 6 .. LOG2T-1 (register index m)
-#pragma unroll
-    for (int h = 1; h < P; h <<= 1)
-#pragma unroll
-      for (int m = 0; m < P; ++m)
-        if (!(m & h)) {
-          const T u = v[m], w = v[m + h];
-          v[m] = u + w;
-          v[m + h] = u - w;
-        }
-    // element e lives at (e >> 6) * ROW + (e & 63)
-#pragma unroll
-    for (int m = 0; m < P; ++m) buf[m * ROW + l] = v[m];
+    const uint64_t gbeta = (uint64_t)(a.row0g / TT + beta);
+    for (int k = l; k < a.s; k += 64) {
+      const uint64_t g = gbeta * (uint64_t)a.s + (uint64_t)k;
+      const uint4 w = stream_words(a.seed, kStreamFct2Rows, g >> 2, a.instance);
+      const uint32_t sel = (uint32_t)g & 3u;
+      const uint32_t wd = sel == 0 ? w.x : sel == 1 ? w.y : sel == 2 ? w.z : w.w;
+      rows[k] = (int32_t)(wd >> (32 - LOG2T));  // floor(w t / 2^32)
+    }
     __syncthreads();
-    // this lane now holds elements mm * 64 + lh * PAD + ll, lh < P
+    // bit m: D is -1 at element m * 64 + l
+    uint64_t smask = 0;
 #pragma unroll
-    for (int lh = 0; lh < P; ++lh) v[lh] = buf[mm * ROW + lh * PAD + ll];
-    // element bits log2(PAD) .. 5 (register index lh)
-#pragma unroll
-    for (int h = 1; h < P; h <<= 1)
-#pragma unroll
-      for (int m = 0; m < P; ++m)
-        if (!(m & h)) {
-          const T u = v[m], w = v[m + h];
-          v[m] = u + w;
-          v[m + h] = u - w;
-        }
-    // element bits 0 .. log2(PAD) - 1 (lane bits of ll)
-#pragma unroll
-    for (int h = 1; h < PAD; h <<= 1)
+    for (int m = 0; m < P; ++m)
+      smask |= (uint64_t)((sw[2 * m + (l >> 5)] >> (l & 31)) & 1u) << m;
+
+    const int mm = l / PAD, ll = l % PAD;  // transposed role of this lane
+    const double zscale = 1.0 / sqrt((double)a.s);
+    for (int j = 0; j < a.q; ++j) {
+      const bool negcol = j >= a.d;  // X = [A, -b]
+      const T* col = negcol ? (const T*)a.b : (const T*)a.A + (size_t)j * a.lda;
+      T v[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        const T p = __shfl_xor(v[m], h, 64);
-        v[m] = (l & h) ? p - v[m] : v[m] + p;
+        const int64_t row = r0 + m * 64 + l;
+        const T x = row < a.n ? col[row] : T(0);
+        v[m] = (((smask >> m) & 1) != 0) != negcol ? -x : x;
       }
-    // each lane rewrites exactly the addresses it read
+      // element bits 6 .. LOG2T-1 (register index m)
 #pragma unroll
-    for (int lh = 0; lh < P; ++lh) buf[mm * ROW + lh * PAD + ll] = v[lh];
-    __syncthreads();
-    for (int k = l; k < a.s; k += 64) {
-      const int e = rows[k];
-      a.Z[(size_t)(beta * a.s + k) * a.zq + j] = (double)buf[(e >> 6) * ROW + (e & 63)] * zscale;
+      for (int h = 1; h < P; h <<= 1)
+#pragma unroll
+        for (int m = 0; m < P; ++m)
+          if (!(m & h)) {
+            const T u = v[m], w = v[m + h];
+            v[m] = u + w;
+            v[m + h] = u - w;
+          }
+      // element e lives at (e >> 6) * ROW + (e & 63)
+#pragma unroll
+      for (int m = 0; m < P; ++m) buf[m * ROW + l] = v[m];
+      __syncthreads();
+      // this lane now holds elements mm * 64 + lh * PAD + ll, lh < P
+#pragma unroll
+      for (int lh = 0; lh < P; ++lh) v[lh] = buf[mm * ROW + lh * PAD + ll];
+      // element bits log2(PAD) .. 5 (register index lh)
+#pragma unroll
+      for (int h = 1; h < P; h <<= 1)
+#pragma unroll
+        for (int m = 0; m < P; ++m)
+          if (!(m & h)) {
+            const T u = v[m], w = v[m + h];
+            v[m] = u + w;
+            v[m + h] = u - w;
+          }
+      // element bits 0 .. log2(PAD) - 1 (lane bits of ll)
+#pragma unroll
+      for (int h = 1; h < PAD; h <<= 1)
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+          const T p = __shfl_xor(v[m], h, 64);
+          v[m] = (l & h) ? p - v[m] : v[m] + p;
+        }
+      // each lane rewrites exactly the addresses it read
+#pragma unroll
+      for (int lh = 0; lh < P; ++lh) buf[mm * ROW + lh * PAD + ll] = v[lh];
+      __syncthreads();
+      for (int k = l; k < a.s; k += 64) {
+        const int e = rows[k];
+        a.Z[(size_t)(beta * a.s + k) * a.zq + j] = (double)buf[(e >> 6) * ROW + (e & 63)] * zscale;
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    // columns q .. zq-1 of Z are zero (the contraction reads whole slices)
+    for (int k = l; k < a.s; k += 64)
+      for (int j = a.q; j < a.zq; ++j) a.Z[(size_t)(beta * a.s + k) * a.zq + j] = 0.0;
   }
-  // columns q .. zq-1 of Z are zero (the contraction reads whole slices)
-  for (int k = l; k < a.s; k += 64)
-    for (int j = a.q; j < a.zq; ++j) a.Z[(size_t)(beta * a.s + k) * a.zq + j] = 0.0;
 }
 
 template <typename TC> __device__ __forceinline__ double fct2_cauchy(uint32_t w);
@@ -139,8 +144,8 @@ __global__ void __launch_bounds__(256) fct2_cauchy_kernel(Fct2Args a) {
   constexpr int MT = 64;  // rows of Z per LDS tile
   __shared__ double zt[MT * QC];
   const int i = blockIdx.y * 256 + threadIdx.x;
-  const int64_t m0 = (int64_t)blockIdx.x * a.kc;
-  const int64_t m1 = min(a.K, m0 + a.kc);
+  const int64_t m0 = a.mbase + (int64_t)blockIdx.x * a.kc;
+  const int64_t m1 = min(a.mend, m0 + a.kc);
   const double* __restrict__ zs = a.Z + (size_t)blockIdx.z * QC;
   const uint64_t ihi = (uint64_t)i << 38;  // (i 2^40 + m) >> 2 for m a multiple of 4
   double acc[QC];
@@ -169,7 +174,7 @@ __global__ void __launch_bounds__(256) fct2_cauchy_kernel(Fct2Args a) {
     }
   }
   if (i >= a.r1) return;
-  double* out = a.partials + (size_t)blockIdx.x * a.r1 * a.q;
+  double* out = a.partials + (size_t)(a.chunk0 + blockIdx.x) * a.r1 * a.q;
 #pragma unroll
   for (int jj = 0; jj < QC; ++jj) {
     const int j = blockIdx.z * QC + jj;
@@ -181,7 +186,7 @@ int fct2_slice_width(int q) { return q <= 8 ? 8 : q <= 17 ? 17 : 33; }
 
 template <typename T>
 static hipError_t launch_fjlt_t(const Fct2Args& a, hipStream_t st) {
-  const dim3 grid((unsigned)a.nb);
+  const dim3 grid((unsigned)(a.fjlt_grid > 0 && a.fjlt_grid < a.nbl ? a.fjlt_grid : a.nbl));
   switch (a.log2t) {
     case 6: hipLaunchKernelGGL((fct2_fjlt_kernel<T, 6>), grid, dim3(64), 0, st, a); break;
     case 7: hipLaunchKernelGGL((fct2_fjlt_kernel<T, 7>), grid, dim3(64), 0, st, a); break;
@@ -209,13 +214,15 @@ static hipError_t launch_cauchy_t(const Fct2Args& a, hipStream_t st) {
 }
 
 hipError_t launch_fct2_fjlt(const Fct2Args& a, bool f64, hipStream_t st) {
-  if (a.s < 1 || a.s > kFct2MaxS || a.s > (1 << a.log2t) || a.nb < 1 || a.nb > 0x7FFFFFFF)
+  if (a.s < 1 || a.s > kFct2MaxS || a.s > (1 << a.log2t) || a.nbl < 1 || a.beta0 < 0 ||
+      a.beta0 + a.nbl > a.nb || a.nb > 0x7FFFFFFF)
     return hipErrorInvalidValue;
   return f64 ? launch_fjlt_t<double>(a, st) : launch_fjlt_t<float>(a, st);
 }
 
 hipError_t launch_fct2_cauchy(const Fct2Args& a, bool f64, hipStream_t st) {
-  if (a.kc < 4 || (a.kc & 3) || a.nchunks < 1 || (int64_t)a.nchunks * a.kc < a.K ||
+  if (a.kc < 4 || (a.kc & 3) || a.nchunks < 1 || (a.mbase & 3) || a.mbase < 0 ||
+      a.mend > a.K || a.mbase + (int64_t)a.nchunks * a.kc < a.mend || a.chunk0 < 0 ||
       a.zq % fct2_slice_width(a.q) != 0)
     return hipErrorInvalidValue;
   return f64 ? launch_cauchy_t<double>(a, st) : launch_cauchy_t<float>(a, st);

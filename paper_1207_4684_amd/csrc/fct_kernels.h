@@ -83,6 +83,9 @@ struct Fct2Args {
   int32_t s;         // rows G keeps per block, 1 <= s <= min(t, kFct2MaxS)
   int32_t log2t;     // block size t = 2^log2t, 6 <= log2t <= 12
   int64_t nb;        // blocks, ceil(n / t)
+  int64_t beta0;     // first block of this launch, which covers nbl blocks
+  int64_t nbl;
+  int64_t fjlt_grid; // workgroups of the FJLT launch (0: one per block)
   int64_t row0g;     // global row of local row 0 (a multiple of t)
   uint64_t seed;
   uint32_t instance;
@@ -91,6 +94,9 @@ struct Fct2Args {
   int32_t r1;
   int64_t K;         // nb s, columns of C
   int64_t kc;        // columns of C per chunk (a multiple of 4)
+  int64_t mbase;     // this launch's columns of C: [mbase, mend), mbase a multiple of 4,
+  int64_t mend;      //   in chunks chunk0 .. chunk0 + nchunks - 1 of the partials
+  int32_t chunk0;
   int32_t nchunks;
   double scale;      // 8 / r1 sqrt(pi t / (2 s))
   double* partials;  // [nchunks][q][r1]

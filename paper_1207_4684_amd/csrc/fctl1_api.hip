@@ -54,6 +54,9 @@ struct fct_ctx {
   int p2_wgs = 0;               // 0: default pass-2 grid cap
   int irls_wgs = 0;             // 0: solver workgroups from the coreset size
   int irls_rows = 0;            // 0: default coreset rows per solver workgroup
+  int fct2_overlap = 0;         // FCT2: contraction of segment k beside the FJLT of k + 1
+  static constexpr int kFct2Segs = 8;
+  hipEvent_t ev_seg[kFct2Segs] = {};
   // batched form: forked streams, events, staging and the cached graph
   static constexpr int kBranches = 4;
   hipStream_t branch[kBranches] = {};
@@ -68,14 +71,14 @@ struct fct_ctx {
 namespace {
 
 // timing brackets around one launch sequence of kind k (0 pass 1, 1 pass 2, 2 solve,
-// 3 FCT2 FJLT blocks, 4 FCT2 Cauchy contraction)
-void prof_begin(fct_ctx* c, int k) {
+// 3 FCT2 FJLT blocks, 4 FCT2 Cauchy contraction), on the context's stream or `st`
+void prof_begin(fct_ctx* c, int k, hipStream_t st = nullptr) {
   if (!c->prof_on || !c->prof_ev[k] || c->prof_n[k] >= fct_ctx::kProfSlots) return;
-  (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k]], c->stream);
+  (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k]], st ? st : c->stream);
 }
-void prof_end(fct_ctx* c, int k) {
+void prof_end(fct_ctx* c, int k, hipStream_t st = nullptr) {
   if (!c->prof_on || !c->prof_ev[k] || c->prof_n[k] >= fct_ctx::kProfSlots) return;
-  (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k] + 1], c->stream);
+  (void)hipEventRecord(c->prof_ev[k][2 * c->prof_n[k] + 1], st ? st : c->stream);
   ++c->prof_n[k];
 }
 
@@ -370,23 +373,38 @@ struct Fct2Plan {
   int log2t;
   int64_t nb, K, kc;
   int nchunks, zq;
+  int nseg;       // segments of blocks (the FJLT of one overlaps the contraction of another)
+  int64_t bseg;   // blocks per segment; bseg * s is a multiple of 4 when nseg > 1
 };
 
-Fct2Plan make_fct2_plan(int64_t n, int q, int t, int s, int r1) {
+// segmented: the rows are split into eight segments so that the contraction of
+// one can run beside the FJLT of the next (FCT_OPT_FCT2_OVERLAP)
+Fct2Plan make_fct2_plan(int64_t n, int q, int t, int s, int r1, bool segmented) {
   Fct2Plan p{};
   p.log2t = ilog2(t);
   p.nb = (n + t - 1) / t;
   p.K = p.nb * s;
   const int qc = fct2_slice_width(q);
   p.zq = (q + qc - 1) / qc * qc;
-  // about 4096 workgroups of 256 rows of C, chunks of at least 64 columns
+  // about 4096 workgroups of 256 rows of C in all, chunks of at least 64 columns
   const int64_t per = (int64_t)((r1 + 255) / 256) * (p.zq / qc);
   int64_t nch = (4096 + per - 1) / per;
   const int64_t most = (p.K + 63) / 64;
   if (nch > most) nch = most;
   if (nch < 1) nch = 1;
   p.kc = ((p.K + nch - 1) / nch + 3) / 4 * 4;
-  p.nchunks = (int)((p.K + p.kc - 1) / p.kc);
+  p.nseg = 1;
+  p.bseg = p.nb;
+  if (segmented && p.nb >= 8 * 64) {
+    p.bseg = ((p.nb + fct_ctx::kFct2Segs - 1) / fct_ctx::kFct2Segs + 3) / 4 * 4;
+    p.nseg = (int)((p.nb + p.bseg - 1) / p.bseg);
+  }
+  p.nchunks = 0;
+  for (int k = 0; k < p.nseg; ++k) {
+    const int64_t m0 = k * p.bseg * s;
+    const int64_t m1 = std::min(p.K, (k + 1) * p.bseg * s);
+    p.nchunks += (int)((m1 - m0 + p.kc - 1) / p.kc);
+  }
   return p;
 }
 
@@ -397,6 +415,8 @@ void carve_fct2(C& cv, const Fct2Plan& p, int q, int r1, bool want_r) {
   cv.template take<double>((size_t)r1 * q);
   if (want_r) cv.template take<double>(qr_work_doubles(r1, q));
 }
+
+int batch_ensure_aux(fct_ctx* c, size_t pinned_bytes);
 
 int check_fct2_args(const fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda,
                     fct_dtype dt, const void* b, int32_t t, int32_t s, int32_t r1, bool want_r) {
@@ -440,12 +460,56 @@ int run_fct2(fct_ctx* c, Carve& cv, const void* A, int64_t n, int32_t d, int64_t
   a.partials = cv.take<double>((size_t)p.nchunks * r1 * q);
   double* Yd = cv.take<double>((size_t)r1 * q);
   const bool f64 = dt == FCT_F64;
+  const bool overlap = p.nseg > 1 && c->fct2_overlap;
+  hipStream_t side = c->stream;
+  if (overlap) {
+    int st = batch_ensure_aux(c, 0);
+    if (st) return st;
+    for (int k = 0; k < p.nseg; ++k)
+      if (!c->ev_seg[k]) HIP_TRY(hipEventCreateWithFlags(&c->ev_seg[k], hipEventDisableTiming));
+    side = c->branch[0];
+    // three single-wave FJLT workgroups per CU keep HBM busy and leave the
+    // rest of each CU to the contraction of the previous segment
+    a.fjlt_grid = 3 * c->cus;
+    // the side stream starts after everything queued so far (scratch reuse)
+    HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+    HIP_TRY(hipStreamWaitEvent(side, c->ev_fork, 0));
+  }
+  // segment k: blocks [k bseg, (k + 1) bseg), columns [k bseg s, (k + 1) bseg s) of C
+  int chunk0 = 0;
   prof_begin(c, 3);
-  HIP_TRY(launch_fct2_fjlt(a, f64, c->stream));
+  for (int k = 0; k < p.nseg; ++k) {
+    a.beta0 = k * p.bseg;
+    a.nbl = std::min(p.nb, (k + 1) * p.bseg) - a.beta0;
+    HIP_TRY(launch_fct2_fjlt(a, f64, c->stream));
+    if (!overlap) continue;
+    HIP_TRY(hipEventRecord(c->ev_seg[k], c->stream));
+    HIP_TRY(hipStreamWaitEvent(side, c->ev_seg[k], 0));
+    if (k == 0) prof_begin(c, 4, side);
+    a.mbase = a.beta0 * s;
+    a.mend = std::min(p.K, (k + 1) * p.bseg * s);
+    a.chunk0 = chunk0;
+    a.nchunks = (int)((a.mend - a.mbase + p.kc - 1) / p.kc);
+    chunk0 += a.nchunks;
+    HIP_TRY(launch_fct2_cauchy(a, f64, side));
+  }
   prof_end(c, 3);
-  prof_begin(c, 4);
-  HIP_TRY(launch_fct2_cauchy(a, f64, c->stream));
-  prof_end(c, 4);
+  if (overlap) {
+    prof_end(c, 4, side);
+    HIP_TRY(hipEventRecord(c->ev_join[0], side));
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join[0], 0));
+  } else {
+    prof_begin(c, 4);
+    for (int k = 0; k < p.nseg; ++k) {
+      a.mbase = k * p.bseg * s;
+      a.mend = std::min(p.K, (k + 1) * p.bseg * s);
+      a.chunk0 = chunk0;
+      a.nchunks = (int)((a.mend - a.mbase + p.kc - 1) / p.kc);
+      chunk0 += a.nchunks;
+      HIP_TRY(launch_fct2_cauchy(a, f64, c->stream));
+    }
+    prof_end(c, 4);
+  }
   HIP_TRY(launch_reduce_partials(a.partials, p.nchunks, r1, q, Y, Yd, c->flags + 0, true,
                                  c->stream, f64 ? 1 : 0));
   if (R) {
@@ -643,6 +707,8 @@ void fct_destroy(fct_ctx* c) {
     if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
   }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  for (int k = 0; k < fct_ctx::kFct2Segs; ++k)
+    if (c->ev_seg[k]) (void)hipEventDestroy(c->ev_seg[k]);
   if (c->bpinned) (void)hipHostFree(c->bpinned);
   if (c->scratch) (void)hipFree(c->scratch);
   if (c->flags) (void)hipFree(c->flags);
@@ -697,6 +763,10 @@ int fct_set_option(fct_ctx* c, int option, int64_t value) {
     case FCT_OPT_SOLVE_ROWS:
       if (value < 0 || value > (1 << 20)) return FCT_ERR_BAD_ARG;
       c->irls_rows = (int)value;
+      return FCT_OK;
+    case FCT_OPT_FCT2_OVERLAP:
+      if (value != 0 && value != 1) return FCT_ERR_BAD_ARG;
+      c->fct2_overlap = (int)value;
       return FCT_OK;
     default:
       return FCT_ERR_BAD_ARG;
@@ -776,7 +846,7 @@ int fct2_sketch(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
   if (st) return st;
   if (!Y && !R) return FCT_ERR_BAD_ARG;
   const int q = d + (b ? 1 : 0);
-  const Fct2Plan p = make_fct2_plan(n, q, t, s, r1);
+  const Fct2Plan p = make_fct2_plan(n, q, t, s, r1, c->fct2_overlap != 0);
   Measure m;
   carve_fct2(m, p, q, r1, R != nullptr);
   if ((st = ensure_scratch(c, m.off))) return st;
@@ -880,7 +950,7 @@ static int coreset_impl(fct_ctx* c, const void* A, const void* b, int64_t n, int
     sub.off = cv.off;
     if (fct2)
       st = run_fct2(c, sub, A, n, d, lda, dt, b, prm->s, prm->s2, prm->r1, prm->seed, nullptr, R,
-                    make_fct2_plan(n, q, prm->s, prm->s2, prm->r1));
+                    make_fct2_plan(n, q, prm->s, prm->s2, prm->r1, c->fct2_overlap != 0));
     else
       st = run_sketch(c, sub, A, n, d, lda, dt, b, prm->s, prm->r1, prm->seed, prm->flags,
                       nullptr, R, nullptr, p);
@@ -926,7 +996,8 @@ static size_t coreset_scratch(const fct_ctx* c, int64_t n, int32_t d, fct_dtype 
   const size_t base = m.off;
   Measure a, bb, cc;
   if (fct2) {
-    carve_fct2(a, make_fct2_plan(n, q, prm->s, prm->s2, prm->r1), q, prm->r1, true);
+    carve_fct2(a, make_fct2_plan(n, q, prm->s, prm->s2, prm->r1, c->fct2_overlap != 0), q,
+               prm->r1, true);
   } else {
     const Pass1Plan p =
         make_pass1_plan(c, n_pad, q, prm->s, prm->r1, esize(dt), prm->flags, &perr);

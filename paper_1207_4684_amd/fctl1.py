@@ -24,7 +24,7 @@ FCT_FLAG_DETERMINISTIC = 2
 FCT_FLAG_GAUSSIAN_PI2 = 4
 FCT_FLAG_FCT2 = 8
 FCT_OPT_PASS1_KERNEL, FCT_OPT_PASS1_WGS_PER_CU, FCT_OPT_PASS1_TILE_THREADS = 1, 2, 3
-FCT_OPT_PASS2_WGS, FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS = 4, 5, 6
+FCT_OPT_PASS2_WGS, FCT_OPT_SOLVE_WGS, FCT_OPT_SOLVE_ROWS, FCT_OPT_FCT2_OVERLAP = 4, 5, 6, 7
 FCT_P1_AUTO, FCT_P1_WAVE, FCT_P1_OWNER, FCT_P1_TILE = 0, 1, 2, 3
 STATUS = {0: "ok", -1: "bad argument", -2: "out of device memory", -3: "non-finite value in input",
           -4: "rank deficient", -5: "HIP runtime error", -6: "coreset larger than capacity"}

@@ -64,6 +64,7 @@ CASES = [
     (9000, 5, 512, 200, 64, np.float64, True),
     (3000, 2, 2048, 1, 16, np.float64, False),
     (100, 4, 4096, 48, 8, np.float32, True),
+    (600000, 5, 1024, 16, 200, np.float32, True),   # 586 blocks: eight overlapped segments
 ]
 
 
@@ -99,6 +100,27 @@ def test_fct2_r_and_reproducibility(F, ctx):
     aY = (S[:, None] * np.abs(Yo)).sum(axis=0)
     bound = 1e-5 * (aY[:, None] + aY[None, :]) + 1e-10 * float(S @ S) + 1e-12 * np.abs(G).max()
     assert np.all(np.abs(Rg.T @ Rg - G) <= bound)
+
+
+def test_fct2_overlap_segments(F, ctx):
+    """The launch that runs the contraction of each eighth of the rows on a
+    second stream beside the FJLT of the next (a capped, grid-strided FJLT
+    grid) against the oracle, run twice (bitwise equal: the partial sums and
+    their order are fixed by the plan), and against the one-launch form."""
+    A, b = data(1 << 20, 6, np.float32, seed=3)
+    Ad, bd = dev(A), dev(b)
+    out = {}
+    for ov in (1, 0, 1):
+        ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, ov)
+        Y, R = F.fct2_sketch(ctx, Ad, bd, 1024, 32, 300, 17)
+        out.setdefault(ov, []).append((host(Y), host(R)))
+    ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 0)
+    (y1, r1), (y3, r3) = out[1]
+    (y0, r0), = out[0]
+    assert np.array_equal(y1, y3) and np.array_equal(r1, r3)
+    Yo, S = fct.fct2_apply(xmat(A, b), 1024, 32, 300, 17, return_scale=True)
+    for y in (y0, y1):
+        assert np.all(np.max(np.abs(y - Yo), axis=1) <= 1e-5 * S)
 
 
 def test_fct2_window_of_columns_is_a_column_of_the_whole(F, ctx):

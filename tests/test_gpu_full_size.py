@@ -4,7 +4,8 @@
   (33,554,432 x 64) and large (268,435,456 x 16), element by element against
   the oracle's, stored in tests/golden/ by make_full_sketches.py (oracle and
   synth only), gated at 1e-5 of each row's l1 mass; R against the oracle's
-  Gram matrix of that sketch.
+  Gram matrix of that sketch.  The same for the FCT2 sketch of each workload
+  (block sizes from the generator's table).
 * lambda on sampled rows for the FP32 and BF16 passes (the oracle evaluates
   those rows from the GPU's R), and the selection given the GPU's lambda
   (over all rows, or a window of rows).
@@ -163,6 +164,32 @@ def check_whole_sketch(F, ctx, L):
     return R
 
 
+def fct2_params(name):
+    """(t, s) of the stored FCT2 sketch of a workload (the generator's table)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_full_sketches",
+                                                  os.path.join(GOLDEN, "make_full_sketches.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.FCT2_PARAMS[name]
+
+
+def check_fct2_whole_sketch(F, ctx, L, name):
+    """FCT2's whole sketch against the oracle's (stored by the generator)."""
+    w = L.w
+    t, s = fct2_params(name)
+    Yo = np.load(os.path.join(GOLDEN, f"fct2_sketch_{w.name}.npy"))
+    S = np.load(os.path.join(GOLDEN, f"fct2_scale_{w.name}.npy"))
+    Y, R = F.fct2_sketch(ctx, L.Ad, L.bd, t, s, w.r1, w.seed)
+    Yg = host(Y).astype(np.float64)
+    err = np.max(np.abs(Yg - Yo), axis=1)
+    print(f"{w.name}: FCT2 (t={t}, s={s}) whole sketch max err / S = {float(np.max(err / S)):.3e}",
+          flush=True)
+    assert np.all(err <= 1e-5 * S), float(np.max(err / S))
+    Rg = host(R)
+    assert np.all(np.diag(Rg) > 0) and np.allclose(np.tril(Rg, -1), 0)
+
+
 # ---- tall ------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
@@ -176,6 +203,10 @@ def test_tall_full_size_sketch_lambda_selection(F, ctx, tall):
     R = check_whole_sketch(F, ctx, tall)
     lam, tot = check_lambda_sampled(F, ctx, tall, R, np.random.default_rng(1))
     check_selection(F, ctx, tall, lam, tot)
+
+
+def test_tall_full_size_fct2_sketch(F, ctx, tall):
+    check_fct2_whole_sketch(F, ctx, tall, "tall")
 
 
 def test_tall_full_size_one_plus_eps(F, ctx, tall):
@@ -197,6 +228,10 @@ def test_precision_full_size_sketch_lambda_selection(F, ctx, precision):
     check_selection(F, ctx, precision, lam, tot, window=(1 << 24, (1 << 24) + (1 << 22)))
 
 
+def test_precision_full_size_fct2_sketch(F, ctx, precision):
+    check_fct2_whole_sketch(F, ctx, precision, "precision")
+
+
 def test_precision_full_size_one_plus_eps(F, ctx, precision):
     check_one_plus_eps(F, ctx, precision)
 
@@ -212,6 +247,10 @@ def test_large_full_size_sketch_lambda_selection(F, ctx, large):
     R = check_whole_sketch(F, ctx, large)
     lam, tot = check_lambda_sampled(F, ctx, large, R, np.random.default_rng(3))
     check_selection(F, ctx, large, lam, tot, window=(3 << 26, (3 << 26) + (1 << 22)))
+
+
+def test_large_full_size_fct2_sketch(F, ctx, large):
+    check_fct2_whole_sketch(F, ctx, large, "large")
 
 
 def test_large_full_size_one_plus_eps(F, ctx, large):
