@@ -358,7 +358,7 @@ def run_workload(F, torch, ctx, w, steps, warmup, flush, bf16=True, ref=True, er
     return rec
 
 
-def bench_fct2(F, torch, ctx, w, Ad, bd, flush, t=4096, s=32, steps=5):
+def bench_fct2(F, torch, ctx, w, Ad, bd, flush, t=4096, s=32, steps=5, overlap=False):
     """The FCT2 sketch Pi1 [A, -b] (block size t, s sampled rows per block,
     r1 of the workload) and the regression that takes its R from it.  Kernel
     times from the library's events: the FJLT blocks read X once and write
@@ -373,22 +373,24 @@ def bench_fct2(F, torch, ctx, w, Ad, bd, flush, t=4096, s=32, steps=5):
     def sketch():
         return F.fct2_sketch(ctx, Ad, bd, t, s, w.r1, w.seed, want_y=False)
     # the default launch (each kernel alone on the device: per-kernel
-    # rooflines), then the option that runs the contraction of one segment
-    # beside the FJLT of the next
+    # rooflines); with ``overlap`` also the option that runs the contraction
+    # of one segment beside the FJLT of the next
     ctx.profile(True)
     times, _ = timed_steps(torch, sketch, steps, 1, flush)
     fj = ctx.profile_read(3)
     ca = ctx.profile_read(4)
     ctx.profile(False)
-    ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 1)
-    t_ov, _ = timed_steps(torch, sketch, steps, 1, flush)
-    ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 0)
+    t_ov = None
+    if overlap:
+        ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 1)
+        t_ov, _ = timed_steps(torch, sketch, steps, 1, flush)
+        ctx.set_option(F.FCT_OPT_FCT2_OVERLAP, 0)
     fj_ms = fj[0] / max(1, fj[1])
     ca_ms = ca[0] / max(1, ca[1])
     fj_bytes = w.n * q * 4 + K * zq * 8
     entries = w.r1 * K
     out = {"t": t, "s": s, "r1": w.r1, "sketch_ms": round(statistics.median(times) * 1e3, 4),
-           "sketch_overlap_option_ms": round(statistics.median(t_ov) * 1e3, 4),
+           "sketch_overlap_option_ms": None if t_ov is None else round(statistics.median(t_ov) * 1e3, 4),
            "fjlt_ms": round(fj_ms, 5), "fjlt_algorithmic_bytes": fj_bytes,
            "fjlt_GBps": round(fj_bytes / (fj_ms * 1e-3) / 1e9, 1),
            "fjlt_frac": round(fj_bytes / (fj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -399,6 +401,10 @@ def bench_fct2(F, torch, ctx, w, Ad, bd, flush, t=4096, s=32, steps=5):
     prm = F.params(s=t, r1=w.r1, r2=w.r2, s_out=w.s_out, seed=w.seed, flags=F.FCT_FLAG_FCT2, s2=s)
     tr, res = timed_steps(torch, lambda: F.l1_regress(ctx, Ad, bd, prm, eps=w.eps), 3, 1, flush)
     out.update({"regress_ms": round(statistics.median(tr) * 1e3, 4), "regress_coreset_rows": int(res[2])})
+    from paper_1207_4684_amd.profile_summary import FCT2_SOURCES, source_sha256
+    tr_b = committed_traffic(source_sha256(FCT2_SOURCES), os.path.join(
+        ROOT, "profiles", f"pmc_fct2_fjlt_{w.name}.txt"))
+    out["fjlt_traffic"] = None if tr_b is None or (t, s) != (4096, 32) else round(tr_b)
     progress(f"{w.name}: FCT2 sketch {out['sketch_ms']} ms (FJLT {out['fjlt_ms']} ms, "
              f"contraction {out['contraction_ms']} ms), regression {out['regress_ms']} ms")
     return out, res[0]
@@ -576,6 +582,8 @@ def main():
     ap.add_argument("--fct2-t", type=int, default=4096,
                     help="FCT2 block size timed on the headline workload (0 = skip)")
     ap.add_argument("--fct2-s", type=int, default=32, help="FCT2 rows sampled per block")
+    ap.add_argument("--fct2-overlap", action="store_true",
+                    help="also time FCT2 with FCT_OPT_FCT2_OVERLAP (segmented, two streams)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 26, help="rows of the CPU baseline's sample")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ref", action="store_true", help="skip the all-rows reference solves")
@@ -599,7 +607,8 @@ def main():
     flush = Flusher(torch)
     head = run_workload(F, torch, ctx, w, args.steps, args.warmup, flush, ref=not args.skip_ref,
                         err_report=w.dtype == "f32", multi=args.multi,
-                        fct2=dict(t=args.fct2_t, s=args.fct2_s) if args.fct2_t > 0 else None)
+                        fct2=dict(t=args.fct2_t, s=args.fct2_s, overlap=args.fct2_overlap)
+                        if args.fct2_t > 0 else None)
     if args.profile_copy_mib > 0:
         src = torch.empty(args.profile_copy_mib << 18, dtype=torch.float32, device="cuda")
         src.fill_(1.0)

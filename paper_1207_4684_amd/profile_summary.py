@@ -31,6 +31,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PASS1_SOURCES = ("csrc/pass1_owner.hip", "csrc/pass1_wave.hip", "csrc/wave_fwht.h",
                  "csrc/fct_device.h")
+FCT2_SOURCES = ("csrc/fct2.hip", "csrc/fct_device.h", "csrc/fct_kernels.h")
+SOURCES = {"pass1": PASS1_SOURCES, "fct2": FCT2_SOURCES}
 
 
 def source_sha256(files=PASS1_SOURCES) -> str:
@@ -121,7 +123,8 @@ def cmd_traffic(args):
     if args.algorithmic_bytes:
         print(f"algorithmic_bytes_per_launch: {args.algorithmic_bytes}")
         print(f"traffic_over_algorithmic: {hbm / args.algorithmic_bytes:.4f}")
-    print(f"source_sha256: {source_sha256()}")
+    print(f"sources: {' '.join(SOURCES[args.sources])}")
+    print(f"source_sha256: {source_sha256(SOURCES[args.sources])}")
 
 
 def cmd_pmc(args):
@@ -189,6 +192,8 @@ def main(argv=None):
                    help="substring of a kernel name; repeat to sum kernels launched together")
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--algorithmic-bytes", type=int, default=0)
+    t.add_argument("--sources", choices=sorted(SOURCES), default="pass1",
+                   help="kernel sources whose hash the summary records")
     t.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer",
                    help="substring naming the copy kernel of known size (the runtime's "
                         "device-to-device copy by default; its largest dispatch is taken)")
