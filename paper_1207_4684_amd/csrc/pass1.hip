@@ -189,8 +189,20 @@ reduce_partials_kernel(const T* __restrict__ part, int nranges, int r1, int q,
   const int64_t idx = (int64_t)blockIdx.x * 64 + i;
   const int64_t tot = (int64_t)r1 * q;
   double s = 0.0;
-  if (idx < tot)
-    for (int rr = g; rr < nranges; rr += kRedGroups) s += (double)part[(size_t)rr * tot + idx];
+  if (idx < tot) {
+    // eight of the wave's ranges are loaded before they are added (in the
+    // same order), so that the loads are in flight together
+    constexpr int U = 8;
+    int rr = g;
+    for (; rr + (U - 1) * kRedGroups < nranges; rr += U * kRedGroups) {
+      T x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = part[(size_t)(rr + u * kRedGroups) * tot + idx];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += (double)x[u];
+    }
+    for (; rr < nranges; rr += kRedGroups) s += (double)part[(size_t)rr * tot + idx];
+  }
   ws[g][i] = s;
   __syncthreads();
   if (g != 0 || idx >= tot) return;

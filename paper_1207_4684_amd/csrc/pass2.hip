@@ -191,6 +191,127 @@ __device__ __forceinline__ float f4_comp(const float4& v, int i) {
 template <int LS>
 __device__ __forceinline__ float* p2_tile_rows(float* L, int i) { return L + i * (16 * LS + 4); }
 
+// Loads of one 64-row tile for the MFMA forms: lane (n4, g) takes rows
+// 64 tt + 4 n4 .. + 3 of column 4 ks + g (FP32, one float4 per column) or of
+// columns 16 ks + 4 g + j (BF16, one 8-byte load per column); columns past q
+// and rows past n read as zero, columns from d on (B) are negated.
+template <int KS>
+__device__ __forceinline__ void p2_load_f32(const float* __restrict__ A, const float* __restrict__ bv,
+                                            int64_t lda, int64_t ldb, int d, int q, int64_t n,
+                                            bool vec, int64_t tt, int n4, int g, float4 (&dst)[KS]) {
+  const int64_t rb = (tt << 6) + 4 * n4;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int c = 4 * ks + g;
+    float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (c < q) {
+      const float* col = c < d ? A + (int64_t)c * lda : bv + (int64_t)(c - d) * ldb;
+      if (vec && rb + 3 < n) {
+        x4 = *reinterpret_cast<const float4*>(col + rb);
+      } else {
+        if (rb < n) x4.x = col[rb];
+        if (rb + 1 < n) x4.y = col[rb + 1];
+        if (rb + 2 < n) x4.z = col[rb + 2];
+        if (rb + 3 < n) x4.w = col[rb + 3];
+      }
+      if (c >= d) x4 = make_float4(-x4.x, -x4.y, -x4.z, -x4.w);
+    }
+    dst[ks] = x4;
+  }
+}
+
+template <int KS>
+__device__ __forceinline__ void p2_load_bf16(const uint16_t* __restrict__ A,
+                                             const uint16_t* __restrict__ bv, int64_t lda,
+                                             int64_t ldb, int d, int q, int64_t n, bool vec,
+                                             int64_t tt, int n4, int g, uint2 (&dst)[KS][4]) {
+  const int64_t rb = (tt << 6) + 4 * n4;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 16 * ks + 4 * g + j;
+      uint2 x4 = make_uint2(0u, 0u);
+      if (c < q) {
+        const uint16_t* col = c < d ? A + (int64_t)c * lda : bv + (int64_t)(c - d) * ldb;
+        if (vec && rb + 3 < n) {
+          x4 = *reinterpret_cast<const uint2*>(col + rb);
+        } else {
+          const uint32_t e0 = rb < n ? col[rb] : 0u, e1 = rb + 1 < n ? col[rb + 1] : 0u;
+          const uint32_t e2 = rb + 2 < n ? col[rb + 2] : 0u, e3 = rb + 3 < n ? col[rb + 3] : 0u;
+          x4 = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+        }
+        if (c >= d) x4 = make_uint2(x4.x ^ 0x80008000u, x4.y ^ 0x80008000u);
+      }
+      dst[ks][j] = x4;
+    }
+}
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima): a tile loaded
+// on the guarded path is complete before the paths join, so the join does not
+// make the prefetching path wait for its own loads of the next tile.
+__device__ __forceinline__ void p2_wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// The same loads for a whole tile of aligned columns (rows 64 tt .. 64 tt + 63
+// inside X), issued without branches so that they can stay in flight while
+// the previous tile is processed: columns past q load column q - 1, and
+// p2_fix_* zeroes them and negates the columns of B once the data is needed.
+template <int KS>
+__device__ __forceinline__ void p2_issue_f32(const float* __restrict__ A, const float* __restrict__ bv,
+                                             int64_t lda, int64_t ldb, int d, int q, int64_t tt,
+                                             int n4, int g, float4 (&raw)[KS]) {
+  const int64_t rb = (tt << 6) + 4 * n4;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int c = min(4 * ks + g, q - 1);
+    const float* col = c < d ? A + (int64_t)c * lda : bv + (int64_t)(c - d) * ldb;
+    raw[ks] = *reinterpret_cast<const float4*>(col + rb);
+  }
+}
+
+template <int KS>
+__device__ __forceinline__ void p2_fix_f32(int d, int q, int g, const float4 (&raw)[KS],
+                                           float4 (&xv)[KS]) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int c = 4 * ks + g;
+    const float sg = c < d ? 1.0f : -1.0f;
+    const float4 x = raw[ks];
+    xv[ks] = c < q ? make_float4(sg * x.x, sg * x.y, sg * x.z, sg * x.w)
+                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
+template <int KS>
+__device__ __forceinline__ void p2_issue_bf16(const uint16_t* __restrict__ A,
+                                              const uint16_t* __restrict__ bv, int64_t lda,
+                                              int64_t ldb, int d, int q, int64_t tt, int n4, int g,
+                                              uint2 (&raw)[KS][4]) {
+  const int64_t rb = (tt << 6) + 4 * n4;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = min(16 * ks + 4 * g + j, q - 1);
+      const uint16_t* col = c < d ? A + (int64_t)c * lda : bv + (int64_t)(c - d) * ldb;
+      raw[ks][j] = *reinterpret_cast<const uint2*>(col + rb);
+    }
+}
+
+template <int KS>
+__device__ __forceinline__ void p2_fix_bf16(int d, int q, int g, const uint2 (&raw)[KS][4],
+                                            uint2 (&xv)[KS][4]) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 16 * ks + 4 * g + j;
+      const uint32_t flip = c < d ? 0u : 0x80008000u;
+      const uint2 x = raw[ks][j];
+      xv[ks][j] = c < q ? make_uint2(x.x ^ flip, x.y ^ flip) : make_uint2(0u, 0u);
+    }
+}
+
 // KS: K-steps of 4 columns compiled in (the smallest of 3, 5, 9, 17 that
 // covers q; columns past q read as zero).
 template <int MT, int KS>
@@ -198,7 +319,8 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
   constexpr int R2P = 16 * MT, LS = R2P + 4;
   __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS + 12];
   __shared__ double red[kP2Threads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index is uniform: readfirstlane lets the tile loop and its choices stay scalar
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r2p = r2_padded(a.r2);
   const float* __restrict__ Mf = reinterpret_cast<const float*>(a.M);
   const float* __restrict__ A = reinterpret_cast<const float*>(a.A);
@@ -214,35 +336,32 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_f32_kernel(Pass2Args a)
       const int k = 4 * ks + (lane >> 4), m = (lane & 15) + 16 * mt;
       am[mt][ks] = (k < a.q && m < r2p) ? Mf[k * r2p + m] : 0.0f;
     }
+  p2_wait_loads();  // M is in registers before the tile loop (no load is pending across it)
   float* L = lds[wave];
   double lsum = 0.0;
   const int64_t ntiles = (a.n + 63) >> 6;
-  for (int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave; t < ntiles;
-       t += (int64_t)gridDim.x * (kP2Threads / 64)) {
+  const int64_t tstride = (int64_t)gridDim.x * (kP2Threads / 64);
+  const int n4 = lane & 15, g = lane >> 4;
+  // rows 64 t + 4 n4 .. + 3 of column 4 ks + g, one float4 per column; MFMA
+  // tile i takes row 64 t + 4 n4 + i
+  // a whole aligned tile's loads are issued before the previous tile's
+  // products (wave-uniform choice), so a wave keeps two tiles in flight
+  float4 raw[KS];
+  int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave;
+  bool pre = vec && t < ntiles && ((t + 1) << 6) <= a.n;
+  if (pre) p2_issue_f32<KS>(A, bv, a.lda, a.ldb, a.d, a.q, t, n4, g, raw);
+  for (; t < ntiles; t += tstride) {
     const int64_t r0 = t << 6;
-    const int n4 = lane & 15, g = lane >> 4;
-    const int64_t rb = r0 + 4 * n4;
-    // rows rb .. rb + 3 of column 4 ks + g, one float4 per column, all issued
-    // before the first product; MFMA tile i takes row rb + i
     float4 xv[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int c = 4 * ks + g;
-      float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (c < a.q) {
-        const float* col = c < a.d ? A + (int64_t)c * a.lda : bv + (int64_t)(c - a.d) * a.ldb;
-        if (vec && rb + 3 < a.n) {
-          x4 = *reinterpret_cast<const float4*>(col + rb);
-        } else {
-          if (rb < a.n) x4.x = col[rb];
-          if (rb + 1 < a.n) x4.y = col[rb + 1];
-          if (rb + 2 < a.n) x4.z = col[rb + 2];
-          if (rb + 3 < a.n) x4.w = col[rb + 3];
-        }
-        if (c >= a.d) x4 = make_float4(-x4.x, -x4.y, -x4.z, -x4.w);
-      }
-      xv[ks] = x4;
+    if (pre) {
+      p2_fix_f32<KS>(a.d, a.q, g, raw, xv);
+    } else {
+      p2_load_f32<KS>(A, bv, a.lda, a.ldb, a.d, a.q, a.n, vec, t, n4, g, xv);
+      p2_wait_loads();
     }
+    const int64_t tn = t + tstride;
+    pre = vec && tn < ntiles && ((tn + 1) << 6) <= a.n;
+    if (pre) p2_issue_f32<KS>(A, bv, a.lda, a.ldb, a.d, a.q, tn, n4, g, raw);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float* Li = p2_tile_rows<LS>(L, i);
@@ -289,7 +408,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
   constexpr int R2P = 16 * MT, LS = R2P + 4;
   __shared__ __align__(16) float lds[kP2Threads / 64][64 * LS + 12];
   __shared__ double red[kP2Threads / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r2p = r2_padded(a.r2);
   const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(a.A);
   const uint16_t* __restrict__ bv = reinterpret_cast<const uint16_t*>(a.b);
@@ -306,36 +425,32 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
         const int k = 16 * ks + 4 * (lane >> 4) + j, m = (lane & 15) + 16 * mt;
         am[mt][ks][j] = (k < a.q && m < r2p) ? (short)a.Mb[k * r2p + m] : (short)0;
       }
+  p2_wait_loads();  // M is in registers before the tile loop (no load is pending across it)
   float* L = lds[wave];
   double lsum = 0.0;
   const int64_t ntiles = (a.n + 63) >> 6;
-  for (int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave; t < ntiles;
-       t += (int64_t)gridDim.x * (kP2Threads / 64)) {
+  const int64_t tstride = (int64_t)gridDim.x * (kP2Threads / 64);
+  const int n4 = lane & 15, g = lane >> 4;
+  // rows 64 t + 4 n4 .. + 3 of columns 16 ks + 4 g + j: one 8-byte load per
+  // column; MFMA tile i takes row 64 t + 4 n4 + i
+  // a whole aligned tile's loads are issued before the previous tile's
+  // products (wave-uniform choice), so a wave keeps two tiles in flight
+  uint2 raw[KS][4];
+  int64_t t = (int64_t)blockIdx.x * (kP2Threads / 64) + wave;
+  bool pre = vec && t < ntiles && ((t + 1) << 6) <= a.n;
+  if (pre) p2_issue_bf16<KS>(A, bv, a.lda, a.ldb, a.d, a.q, t, n4, g, raw);
+  for (; t < ntiles; t += tstride) {
     const int64_t r0 = t << 6;
-    const int n4 = lane & 15, g = lane >> 4;
-    const int64_t rb = r0 + 4 * n4;
-    // rows rb .. rb + 3 of columns 16 ks + 4 g + j: one 8-byte load per
-    // column; MFMA tile i takes row rb + i
-    uint2 xv[KS][4];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = 16 * ks + 4 * g + j;
-        uint2 x4 = make_uint2(0u, 0u);
-        if (c < a.q) {
-          const uint16_t* col = c < a.d ? A + (int64_t)c * a.lda : bv + (int64_t)(c - a.d) * a.ldb;
-          if (vec && rb + 3 < a.n) {
-            x4 = *reinterpret_cast<const uint2*>(col + rb);
-          } else {
-            const uint32_t e0 = rb < a.n ? col[rb] : 0u, e1 = rb + 1 < a.n ? col[rb + 1] : 0u;
-            const uint32_t e2 = rb + 2 < a.n ? col[rb + 2] : 0u, e3 = rb + 3 < a.n ? col[rb + 3] : 0u;
-            x4 = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
-          }
-          if (c >= a.d) x4 = make_uint2(x4.x ^ 0x80008000u, x4.y ^ 0x80008000u);
-        }
-        xv[ks][j] = x4;
-      }
+    uint2 xc[KS][4];
+    if (pre) {
+      p2_fix_bf16<KS>(a.d, a.q, g, raw, xc);
+    } else {
+      p2_load_bf16<KS>(A, bv, a.lda, a.ldb, a.d, a.q, a.n, vec, t, n4, g, xc);
+      p2_wait_loads();
+    }
+    const int64_t tn = t + tstride;
+    pre = vec && tn < ntiles && ((tn + 1) << 6) <= a.n;
+    if (pre) p2_issue_bf16<KS>(A, bv, a.lda, a.ldb, a.d, a.q, tn, n4, g, raw);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float* Li = p2_tile_rows<LS>(L, i);
@@ -344,7 +459,7 @@ __global__ void __launch_bounds__(kP2Threads) pass2_mfma_bf16_kernel(Pass2Args a
       for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint32_t w = (i < 2) ? xv[ks][j].x : xv[ks][j].y;
+          const uint32_t w = (i < 2) ? xc[ks][j].x : xc[ks][j].y;
           xb[ks][j] = (short)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
         }
 #pragma unroll
