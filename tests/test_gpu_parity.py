@@ -205,6 +205,7 @@ def test_nonfinite_reported(F, ctx):
 # ---- pass 2 ----------------------------------------------------------------
 
 @pytest.mark.parametrize("n,d,s,r1,r2,dtype", [(65536, 16, 64, 512, 8, np.float64),
+                                               (1200000, 8, 64, 256, 8, np.float64),  # FP64 grid > 1024 workgroups
                                                (100003, 32, 256, 2048, 16, np.float32),
                                                (70000, 64, 512, 4096, 24, np.float32),
                                                (30000, 5, 64, 64, 3, np.float32),
