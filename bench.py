@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # second (one wave64 VALU instruction takes 4 cycles of a 16-lane SIMD)
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # VALU instructions per C entry of the FCT2 contraction's inner loop (the
-# 17-column slice compiled for gfx950: 244 per Philox call of 4 entries, 68 of
-# them FP64 FMAs): 44 to draw and transform the variate plus one FMA per column
-FCT2_GEN_VALU_PER_ENTRY = 44
+# 17-column slice compiled for gfx950: 228 per Philox call of 4 entries, 68 of
+# them FP64 FMAs): 40 to draw and transform the variate plus one FMA per column
+FCT2_GEN_VALU_PER_ENTRY = 40
 CHUNK = 1 << 20
 
 
