@@ -44,8 +44,11 @@ def source_sha256(files=PASS1_SOURCES) -> str:
 
 
 def kernel_stats(db: str, match: str | None = None):
+    """Per kernel: calls, total ms, mean, min, max, median and the mean over
+    all dispatches but the first (the first launch of a kernel in a process
+    also pays its one-time set-up; a benchmark's warmup steps absorb it) in us."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, end - start from kernels").fetchall()
+    rows = con.execute("select name, end - start from kernels order by start").fetchall()
     con.close()
     agg: dict[str, list[float]] = {}
     for name, dur in rows:
@@ -54,7 +57,11 @@ def kernel_stats(db: str, match: str | None = None):
         agg.setdefault(name, []).append(float(dur))
     out = []
     for name, d in agg.items():
-        out.append((name, len(d), sum(d) / 1e6, sum(d) / len(d) / 1e3, min(d) / 1e3, max(d) / 1e3))
+        srt = sorted(d)
+        med = srt[len(srt) // 2] if len(srt) % 2 else 0.5 * (srt[len(srt) // 2 - 1] + srt[len(srt) // 2])
+        rest = d[1:] if len(d) > 1 else d
+        out.append((name, len(d), sum(d) / 1e6, sum(d) / len(d) / 1e3, min(d) / 1e3, max(d) / 1e3,
+                    med / 1e3, sum(rest) / len(rest) / 1e3))
     out.sort(key=lambda r: -r[2])
     return out
 
@@ -78,9 +85,10 @@ def _short(name: str, width: int = 90) -> str:
 
 def cmd_stats(args):
     print(f"# kernel trace summary of {os.path.basename(args.db)}")
-    print(f"{'kernel':90s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}")
-    for name, n, tot, avg, mn, mx in kernel_stats(args.db, args.match):
-        print(f"{_short(name):90s} {n:6d} {tot:10.3f} {avg:10.2f} {mn:10.2f} {mx:10.2f}")
+    print(f"{'kernel':90s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+          f"{'median_us':>10s} {'avg_after_first_us':>18s}")
+    for name, n, tot, avg, mn, mx, med, avg1 in kernel_stats(args.db, args.match):
+        print(f"{_short(name):90s} {n:6d} {tot:10.3f} {avg:10.2f} {mn:10.2f} {mx:10.2f} {med:10.2f} {avg1:18.2f}")
 
 
 def _copy_value(table, pattern):
