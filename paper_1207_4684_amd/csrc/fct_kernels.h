@@ -210,13 +210,21 @@ struct IrlsArgs {
   double* x_out;
   double* obj_out;
   int* status;
+  int wg0;         // batched form with a block map: first block of the instance in its launch
+  int nwg;         //   and its workgroups
 };
-// Batched form: one workgroup per instance (all of one element type); work
-// of irls_batched_work_doubles(d) doubles per instance, barrier words at
-// irls_batched_bar(work, d); arr is a device array of count instances.
-size_t irls_batched_work_doubles(int d);
-unsigned* irls_batched_bar(double* work, int d);
-hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStream_t st);
+// Batched form (all of one element type): arr is a device array of count
+// instances; each has work of irls_batched_work_doubles(d, nwg) doubles and
+// its barrier words at irls_batched_bar(work, d, nwg).  Without binst, block
+// b solves instance b alone (nwg = 1); with it, block b works on instance
+// binst[b] (workgroup b - wg0 of its nwg), and nblocks must not exceed what
+// the device holds at once (irls_max_resident_wgs).  reset clears every
+// instance's barrier and status first.
+size_t irls_batched_work_doubles(int d, int nwg = 1);
+unsigned* irls_batched_bar(double* work, int d, int nwg = 1);
+int irls_max_resident_wgs(int cus);
+hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStream_t st,
+                               const int* binst = nullptr, int nblocks = 0, bool reset = true);
 // Persistent cooperative IRLS: S_hint (host) sizes the grid, the device count
 // S_dev (clamped to cap) is the number of rows; x_out[d], obj_out[1].
 hipError_t launch_irls(const void* At, const void* bt, const double* w, const int64_t* S_dev,

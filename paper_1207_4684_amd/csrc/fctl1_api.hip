@@ -1221,6 +1221,13 @@ struct BatchItem {
   int64_t cap;
   size_t off;     // byte offset of the instance's region in the scratch arena
   size_t bytes;
+  int nwg = 1;    // workgroups of the instance's solve
+};
+
+// Block maps of the batched solve: the instances with several workgroups
+// (one launch, big.size() blocks), then the rest (one block each).
+struct BatchSolvePlan {
+  std::vector<int> big, small;
 };
 
 // The FCT1 block size of the paper's experiments (section "Numerical
@@ -1257,7 +1264,7 @@ int batch_ensure_aux(fct_ctx* c, size_t pinned_bytes) {
 // and the collection of outputs on the context stream.
 int batch_enqueue(fct_ctx* c, const fct_instance* inst, int count, fct_dtype dt,
                   const std::vector<BatchItem>& items, const IrlsArgs* args_dev, double* out_dev,
-                  size_t out_bytes) {
+                  size_t out_bytes, const BatchSolvePlan& sp, const int* map_dev) {
   const size_t es = esize(dt);
   HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
   for (int k = 0; k < fct_ctx::kBranches; ++k) HIP_TRY(hipStreamWaitEvent(c->branch[k], c->ev_fork, 0));
@@ -1274,7 +1281,7 @@ int batch_enqueue(fct_ctx* c, const fct_instance* inst, int count, fct_dtype dt,
     char* bt = cv.take<char>((size_t)it.cap * es);
     double* w = cv.take<double>((size_t)it.cap);
     int64_t* idx = cv.take<int64_t>((size_t)it.cap);
-    cv.take<double>(irls_batched_work_doubles(d));
+    cv.take<double>(irls_batched_work_doubles(d, it.nwg));
     cv.take<double>(72);
     cv.take<int>(4);
     Carve rest(c->scratch);
@@ -1294,7 +1301,14 @@ int batch_enqueue(fct_ctx* c, const fct_instance* inst, int count, fct_dtype dt,
     HIP_TRY(hipEventRecord(c->ev_join[k], c->branch[k]));
     HIP_TRY(hipStreamWaitEvent(main, c->ev_join[k], 0));
   }
-  HIP_TRY(launch_irls_batched(args_dev, count, dt == FCT_F64, main));
+  if (sp.big.empty()) {
+    HIP_TRY(launch_irls_batched(args_dev, count, dt == FCT_F64, main));
+  } else {
+    HIP_TRY(launch_irls_batched(args_dev, count, dt == FCT_F64, main, map_dev, (int)sp.big.size(), true));
+    if (!sp.small.empty())
+      HIP_TRY(launch_irls_batched(args_dev, count, dt == FCT_F64, main, map_dev + sp.big.size(),
+                                  (int)sp.small.size(), false));
+  }
   hipLaunchKernelGGL(batch_collect_kernel, dim3(count), dim3(64), 0, main, args_dev, count, out_dev);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->bpinned, out_dev, out_bytes, hipMemcpyDeviceToHost, main));
@@ -1335,21 +1349,56 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
     fct_params& prm = items[i].prm;
     if (prm.s == 0) prm.s = batch_block_size(inst[i].d);
   }
-  size_t total = 0;
   for (int i = 0; i < count; ++i) {
     fct_params& prm = items[i].prm;
     if ((st = check_params(&prm, inst[i].d + 1))) return st;
-    const int d = inst[i].d;
     int64_t cap = 2 * prm.s_out + 8 * (int64_t)std::sqrt((double)prm.s_out) + 1024;
     if (cap > inst[i].n) cap = inst[i].n;
     items[i].cap = cap;
+  }
+  // The solve of an instance costs about cap (d + 1)^2 per reweighting.  One
+  // workgroup holds a whole CU (its LDS), so with one each the largest
+  // instances finish long after the rest.  The instances within 4x of the
+  // largest cost get several workgroups each (as many as the device holds at
+  // once, shared out, at most one per 256 coreset rows) in a launch of their
+  // own; the rest follow, one workgroup each.
+  BatchSolvePlan sp;
+  {
+    std::vector<double> cost((size_t)count);
+    double mx = 0.0;
+    for (int i = 0; i < count; ++i) {
+      cost[i] = (double)items[i].cap * (inst[i].d + 1) * (inst[i].d + 1);
+      mx = std::max(mx, cost[i]);
+    }
+    int nbig = 0;
+    for (int i = 0; i < count; ++i) nbig += cost[i] * 4.0 >= mx;
+    const int resident = irls_max_resident_wgs(c->cus);
+    const int per = nbig > 0 ? resident / nbig : 0;
+    if (nbig < count && per >= 2) {
+      for (int i = 0; i < count; ++i) {
+        if (cost[i] * 4.0 >= mx) {
+          const int byrows = (int)std::max<int64_t>(1, items[i].cap / 256);
+          items[i].nwg = std::min(std::min(per, byrows), 64);
+          for (int k = 0; k < items[i].nwg; ++k) sp.big.push_back(i);
+        } else {
+          sp.small.push_back(i);
+        }
+      }
+      if (sp.big.empty()) sp.small.clear();
+    }
+  }
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    fct_params& prm = items[i].prm;
+    const int d = inst[i].d;
+    const int64_t cap = items[i].cap;
     Measure m;
     m.take<int64_t>(1);
     m.take<char>((size_t)cap * d * es);
     m.take<char>((size_t)cap * es);
     m.take<double>((size_t)cap);
     m.take<int64_t>((size_t)cap);
-    m.take<double>(irls_batched_work_doubles(d));
+    m.take<double>(irls_batched_work_doubles(d, items[i].nwg));
     m.take<double>(72);
     m.take<int>(4);
     const size_t bytes = m.off + coreset_scratch(c, inst[i].n, d, dt, &prm, inst[i].A_lowp != nullptr) + 512;
@@ -1358,14 +1407,17 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
     total += (bytes + 255) & ~size_t(255);
   }
   const size_t args_off = total;
-  total += ((size_t)count * sizeof(IrlsArgs) + 255) & ~size_t(255);
+  const size_t map_count = sp.big.size() + sp.small.size();
+  const size_t args_bytes = (size_t)count * sizeof(IrlsArgs) + map_count * sizeof(int);
+  total += (args_bytes + 255) & ~size_t(255);
   const size_t out_off = total;
   const size_t out_bytes = (size_t)count * 72 * sizeof(double);
   total += out_bytes + 256;
   if ((st = ensure_scratch(c, total))) return st;
-  const size_t pin_bytes = (size_t)count * sizeof(IrlsArgs) > out_bytes ? (size_t)count * sizeof(IrlsArgs) : out_bytes;
+  const size_t pin_bytes = args_bytes > out_bytes ? args_bytes : out_bytes;
   if ((st = batch_ensure_aux(c, pin_bytes))) return st;
   IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(c->scratch + args_off);
+  int* map_dev = reinterpret_cast<int*>(c->scratch + args_off + (size_t)count * sizeof(IrlsArgs));
   double* out_dev = reinterpret_cast<double*>(c->scratch + out_off);
   // per-instance solver arguments (pointers into each instance's region)
   std::vector<IrlsArgs> args((size_t)count);
@@ -1379,18 +1431,34 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
     a.bt = cv.take<char>((size_t)items[i].cap * es);
     a.w = cv.take<double>((size_t)items[i].cap);
     cv.take<int64_t>((size_t)items[i].cap);
-    double* work = cv.take<double>(irls_batched_work_doubles(d));
+    const int nwg = items[i].nwg;
+    double* work = cv.take<double>(irls_batched_work_doubles(d, nwg));
     double* outv = cv.take<double>(72);
     a.status = cv.take<int>(4);
     a.cap = items[i].cap;
     a.ldat = items[i].cap;
     a.d = d;
     a.iters = items[i].prm.irls_iters;
-    a.row_target = 1 << 30;
+    // one workgroup takes every row; several share them about evenly
+    a.row_target = nwg > 1 ? (int)((items[i].cap + nwg - 1) / nwg) : 1 << 30;
     a.part = work;
-    a.bar = irls_batched_bar(work, d);
+    a.bar = irls_batched_bar(work, d, nwg);
     a.x_out = outv;
     a.obj_out = outv + 64;
+    a.wg0 = 0;
+    a.nwg = nwg;
+  }
+  // block maps: each big instance's first block, then the small ones in turn
+  std::vector<int> map;
+  map.reserve(map_count);
+  for (size_t b = 0; b < sp.big.size(); ++b) {
+    const int i = sp.big[b];
+    if (b == 0 || sp.big[b - 1] != i) args[i].wg0 = (int)b;
+    map.push_back(i);
+  }
+  for (size_t b = 0; b < sp.small.size(); ++b) {
+    args[sp.small[b]].wg0 = (int)b;
+    map.push_back(sp.small[b]);
   }
   // signature of this batch: instances, parameters, arena
   std::vector<char> sig;
@@ -1410,8 +1478,9 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
   const bool replay = c->bgraph && sig == c->bsig;
   if (!replay) {
     std::memcpy(c->bpinned, args.data(), (size_t)count * sizeof(IrlsArgs));
-    HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)count * sizeof(IrlsArgs),
-                           hipMemcpyHostToDevice, c->stream));
+    if (!map.empty())
+      std::memcpy((char*)c->bpinned + (size_t)count * sizeof(IrlsArgs), map.data(), map.size() * sizeof(int));
+    HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, args_bytes, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->bgraph) {
       (void)hipGraphExecDestroy(c->bgraph);
@@ -1421,7 +1490,7 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
     // capture; if the runtime refuses, run the same sequence eagerly
     bool captured = false;
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
-      const int est = batch_enqueue(c, inst, count, dt, items, args_dev, out_dev, out_bytes);
+      const int est = batch_enqueue(c, inst, count, dt, items, args_dev, out_dev, out_bytes, sp, map_dev);
       hipGraph_t g = nullptr;
       const hipError_t ee = hipStreamEndCapture(c->stream, &g);
       if (est == FCT_OK && ee == hipSuccess && g) {
@@ -1438,7 +1507,8 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
     if (captured) {
       HIP_TRY(hipGraphLaunch(c->bgraph, c->stream));
     } else {
-      if ((st = batch_enqueue(c, inst, count, dt, items, args_dev, out_dev, out_bytes))) return st;
+      if ((st = batch_enqueue(c, inst, count, dt, items, args_dev, out_dev, out_bytes, sp, map_dev)))
+        return st;
     }
   } else {
     HIP_TRY(hipGraphLaunch(c->bgraph, c->stream));

@@ -283,14 +283,19 @@ __device__ __noinline__ bool gj_solve_wide(const double* G, const double* rhs, c
   return gj_solve<kGjMax>(er, ec, G, rhs, sc, gjcol2, gjrow2, gjt, gjd, d, z);
 }
 
-// BATCH: every workgroup solves its own instance, arr[blockIdx.x], alone (one
-// workgroup per instance, with its own barrier word, partials and status);
-// otherwise the grid cooperates on the instance a0.
+// BATCH: every instance has its own barrier word, partials and status.
+// Without binst, workgroup b solves instance arr[b] alone; with it, block b
+// belongs to instance binst[b] as its workgroup b - wg0 of nwg, and the
+// instance's workgroups meet at its own barrier (the launch keeps the grid
+// within what the device holds at once).  Otherwise the grid cooperates on
+// the instance a0.
 template <typename T, bool BATCH>
-__global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const IrlsArgs* __restrict__ arr) {
-  const IrlsArgs a = BATCH ? arr[blockIdx.x] : a0;
-  const int wg = BATCH ? 0 : (int)blockIdx.x;
-  const int gcount = BATCH ? 1 : (int)gridDim.x;
+__global__ void __launch_bounds__(kIrlsThreads) irls_kernel(IrlsArgs a0, const IrlsArgs* __restrict__ arr,
+                                                           const int* __restrict__ binst) {
+  const int inst = BATCH ? (binst ? binst[blockIdx.x] : (int)blockIdx.x) : 0;
+  const IrlsArgs a = BATCH ? arr[inst] : a0;
+  const int wg = BATCH ? (binst ? (int)blockIdx.x - a.wg0 : 0) : (int)blockIdx.x;
+  const int gcount = BATCH ? (binst ? a.nwg : 1) : (int)gridDim.x;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int flag_stop, flag_bad, flag_ok, flag_best;
   const IrlsGeom g(a.d, sizeof(T));
@@ -581,27 +586,41 @@ __global__ void irls_reset_batched_kernel(const IrlsArgs* __restrict__ arr, int 
   }
 }
 
-size_t irls_batched_work_doubles(int d) {
+size_t irls_batched_work_doubles(int d, int nwg) {
   const IrlsGeom g(d, sizeof(double));
-  return 2 * (size_t)g.pstride + 8;
+  return 2 * (size_t)nwg * g.pstride + 8;
 }
 
-unsigned* irls_batched_bar(double* work, int d) {
-  return reinterpret_cast<unsigned*>(work + irls_batched_work_doubles(d) - 8);
+unsigned* irls_batched_bar(double* work, int d, int nwg) {
+  return reinterpret_cast<unsigned*>(work + irls_batched_work_doubles(d, nwg) - 8);
 }
 
-hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStream_t st) {
+int irls_max_resident_wgs(int cus) {
+  int per = 0;
+  const void* fn = (const void*)irls_kernel<float, true>;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kIrlsLdsBytes) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kIrlsThreads, kIrlsLdsBytes) != hipSuccess)
+    return 0;
+  return per * cus;
+}
+
+hipError_t launch_irls_batched(const IrlsArgs* arr, int count, bool f64, hipStream_t st,
+                               const int* binst, int nblocks, bool reset) {
   if (count <= 0) return hipSuccess;
   const size_t lds = kIrlsLdsBytes;
   const void* fn = f64 ? (const void*)irls_kernel<double, true> : (const void*)irls_kernel<float, true>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   IrlsArgs none{};
-  hipLaunchKernelGGL(irls_reset_batched_kernel, dim3((count + 63) / 64), dim3(64), 0, st, arr, count);
+  if (reset)
+    hipLaunchKernelGGL(irls_reset_batched_kernel, dim3((count + 63) / 64), dim3(64), 0, st, arr, count);
+  const int grid = binst ? nblocks : count;
+  if (grid <= 0) return hipGetLastError();
   if (f64)
-    hipLaunchKernelGGL((irls_kernel<double, true>), dim3(count), dim3(kIrlsThreads), lds, st, none, arr);
+    hipLaunchKernelGGL((irls_kernel<double, true>), dim3(grid), dim3(kIrlsThreads), lds, st, none, arr, binst);
   else
-    hipLaunchKernelGGL((irls_kernel<float, true>), dim3(count), dim3(kIrlsThreads), lds, st, none, arr);
+    hipLaunchKernelGGL((irls_kernel<float, true>), dim3(grid), dim3(kIrlsThreads), lds, st, none, arr, binst);
   return hipGetLastError();
 }
 
@@ -646,7 +665,8 @@ hipError_t launch_irls(const void* At, const void* bt, const double* w, const in
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(irls_reset_kernel, dim3(1), dim3(64), 0, st, a.bar);
   const IrlsArgs* none = nullptr;
-  void* args[] = {&a, &none};
+  const int* nomap = nullptr;
+  void* args[] = {&a, &none, &nomap};
   return hipLaunchCooperativeKernel(fn, dim3(P), dim3(kIrlsThreads), args, (unsigned)lds, st);
 }
 
