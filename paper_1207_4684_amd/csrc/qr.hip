@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(const double* __re
   double* Pm = reinterpret_cast<double*>(smem_raw);
   __shared__ double red[kQrThreads / 64];
   __shared__ double wdot[128];
-  __shared__ double sh_beta, sh_rkk;
+  __shared__ double sh_beta, sh_rkk, sh_sigma;
   const int p = blockIdx.x;
   const int64_t r0 = (int64_t)p * P;
   const int m = (int)min((int64_t)P, m_total - r0);
@@ -42,16 +42,26 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(const double* __re
   }
   __syncthreads();
   const int kmax = min(m, q);
-  for (int k = 0; k < kmax; ++k) {
-    double* colk = Pm + (size_t)k * m;
+  // sigma_k = sum over rows i > k of P[i, k]^2: for column 0 from all threads;
+  // for column k + 1 by wave 0 while it applies reflection k to that column
+  {
     double part = 0.0;
-    for (int i = k + 1 + tid; i < m; i += kQrThreads) part += colk[i] * colk[i];
+    for (int i = 1 + tid; i < m; i += kQrThreads) part += Pm[i] * Pm[i];
     part = wave_sum(part);
     if (lane == 0) red[wave] = part;
     __syncthreads();
     if (tid == 0) {
       double sigma = 0.0;
       for (int w = 0; w < nw; ++w) sigma += red[w];
+      sh_sigma = sigma;
+    }
+  }
+  for (int k = 0; k < kmax; ++k) {
+    double* colk = Pm + (size_t)k * m;
+    if (tid == 0) {
+      // R_{k-1,k-1} replaces v_{k-1} now that reflection k - 1 is applied
+      if (k > 0) Pm[(size_t)(k - 1) * m + (k - 1)] = sh_rkk;
+      const double sigma = sh_sigma;
       const double alpha = colk[k];
       const double norm = sqrt(alpha * alpha + sigma);
       if (norm == 0.0) {
@@ -80,13 +90,28 @@ __global__ void __launch_bounds__(kQrThreads) qr_panel_kernel(const double* __re
       for (int j = k + 1 + wave; j < q; j += nw) {
         double* colj = Pm + (size_t)j * m;
         const double wj = wdot[j];
-        for (int i = k + lane; i < m; i += 64) colj[i] -= colk[i] * wj;
+        double part = 0.0;
+        for (int i = k + lane; i < m; i += 64) {
+          const double v = colj[i] - colk[i] * wj;
+          colj[i] = v;
+          if (i > k + 1) part += v * v;
+        }
+        if (j == k + 1) {  // wave 0
+          part = wave_sum(part);
+          if (lane == 0) sh_sigma = part;
+        }
       }
+    } else if (wave == 0 && k + 1 < q) {
+      const double* colj = Pm + (size_t)(k + 1) * m;
+      double part = 0.0;
+      for (int i = k + 2 + lane; i < m; i += 64) part += colj[i] * colj[i];
+      part = wave_sum(part);
+      if (lane == 0) sh_sigma = part;
     }
     __syncthreads();
-    if (tid == 0) colk[k] = sh_rkk;
-    __syncthreads();
   }
+  if (tid == 0 && kmax > 0) Pm[(size_t)(kmax - 1) * m + (kmax - 1)] = sh_rkk;
+  __syncthreads();
   for (int idx = tid; idx < q * q; idx += kQrThreads) {
     const int i = idx % q, j = idx / q;
     const double v = (i <= j && i < m) ? Pm[i + (size_t)j * m] : 0.0;
