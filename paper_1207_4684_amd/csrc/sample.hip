@@ -5,7 +5,7 @@
 // Row i is kept iff its stream-3 word w_i satisfies w_i < floor(p_i 2^32),
 // with p_i formed in FP64 (the event "uniform < p_i" on the 2^-32 grid).
 // Kept rows are listed in ascending order by one pass over lambda: a
-// workgroup takes the next 8192-row tile from a ticket counter, decides its
+// workgroup takes the next 16384-row tile from a ticket counter, decides its
 // rows, publishes its count, and finds the count of all earlier tiles by
 // looking back over their published counts and prefixes (a decoupled
 // look-back scan); then it writes its rows at that offset after an in-tile
@@ -18,7 +18,7 @@
 namespace fctl1 {
 
 static constexpr int kSelThreads = 256;
-static constexpr int kSelRowsPerThread = 32;
+static constexpr int kSelRowsPerThread = 64;
 static constexpr int kSelRows = kSelThreads * kSelRowsPerThread;
 
 int select_grid(int64_t n) { return (int)((n + kSelRows - 1) / kSelRows); }
@@ -31,14 +31,14 @@ __device__ __forceinline__ uint64_t threshold(float lam, double s_out, double to
   return (uint64_t)(t < 4294967296.0 ? t : 4294967296.0);
 }
 
-// Keep mask of this thread's 32 consecutive rows (bit k = row base + k);
-// base is a multiple of 32, so a whole group is eight 16-byte loads.  The
+// Keep mask of this thread's 64 consecutive rows (bit k = row base + k);
+// base is a multiple of 64, so a whole group is sixteen 16-byte loads.  The
 // decision w < floor(p 2^32) holds iff the unfloored p 2^32 >= w + 1.  That
 // value is first estimated as lambda * (s_out 2^32 / sum lambda), within a few
 // units of 2^-53 of it; the estimate settles the decision unless it lies
 // within a relative 1e-12 of w + 1, and only those rare rows (and every row
 // when p is written out) evaluate p itself as the oracle does.
-__device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base, double total,
+__device__ __forceinline__ uint64_t keep_mask(const SelectArgs& a, int64_t base, double total,
                                               bool write_p) {
   float lam[kSelRowsPerThread];
   if (base + kSelRowsPerThread <= a.n) {
@@ -57,7 +57,7 @@ __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base,
   }
   const bool quick = !write_p && total > 0.0;
   const double scale = quick ? a.s_out * 4294967296.0 / total : 0.0;
-  uint32_t mask = 0;
+  uint64_t mask = 0;
 #pragma unroll
   for (int qd = 0; qd < kSelRowsPerThread / 4; ++qd) {
     const int64_t r0 = base + 4 * qd;
@@ -79,7 +79,7 @@ __device__ __forceinline__ uint32_t keep_mask(const SelectArgs& a, int64_t base,
           if (write_p && a.p_out) a.p_out[i] = (float)p;
           keep = (uint64_t)ws[k] < t;
         }
-        if (keep) mask |= 1u << (4 * qd + k);
+        if (keep) mask |= 1ull << (4 * qd + k);
       }
     }
   }
@@ -147,9 +147,9 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(SelectArgs a, int n
   const int tile = s_tile;
   const double total = *a.sum_lambda;
   const int64_t base = (int64_t)tile * kSelRows + (int64_t)threadIdx.x * kSelRowsPerThread;
-  uint32_t m = keep_mask(a, base, total, a.p_out != nullptr);
+  uint64_t m = keep_mask(a, base, total, a.p_out != nullptr);
   int tot;
-  const int pre = block_exclusive_scan(__popc(m), sh, &tot);
+  const int pre = block_exclusive_scan(__popcll(m), sh, &tot);
 
   if (threadIdx.x < 64) {
     // wave 0: publish, then add the counts of the tiles before this one,
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kSelThreads) select_kernel(SelectArgs a, int n
   if (tile == nb - 1 && threadIdx.x == 0) *a.S = first + tot;
   int64_t pos = first + pre;
   while (m) {
-    const int k = __ffs(m) - 1;
+    const int k = __ffsll((long long)m) - 1;
     m &= m - 1;
     const int64_t i = base + k;
     if (pos < a.cap) {
