@@ -1535,6 +1535,52 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
   return first;
 }
 
+// Workgroups per instance of a batched solve over `count` alike instances
+// of at most cap coreset rows: the workgroups the device holds at once,
+// shared out, at most one per 256 rows and 64 (1: one workgroup each).
+static int alike_solve_wgs(const fct_ctx* c, int count, int64_t cap) {
+  const int resident = irls_max_resident_wgs(c->cus);
+  int64_t w = count > 0 ? resident / count : 1;
+  w = std::min<int64_t>(w, std::max<int64_t>(1, cap / 256));
+  w = std::min<int64_t>(w, 64);
+  return (int)std::max<int64_t>(w, 1);
+}
+
+// bytes of `count` solver arguments followed by their block map
+static size_t solve_args_bytes(int count, int nwg) {
+  return (size_t)count * sizeof(IrlsArgs) + (nwg > 1 ? (size_t)count * nwg * sizeof(int) : 0);
+}
+
+// coreset rows per workgroup: all of them for one, an even share for several
+static int solve_row_target(int64_t cap, int nwg) {
+  return nwg > 1 ? (int)((cap + nwg - 1) / nwg) : 1 << 30;
+}
+
+// Instance k's blocks are k nwg .. k nwg + nwg - 1: its first block, the
+// block map after the arguments, both copied to the device (through the
+// pinned block, which the caller then waits for).
+static int upload_solve_args(fct_ctx* c, std::vector<IrlsArgs>& args, int nwg, IrlsArgs* args_dev) {
+  const int count = (int)args.size();
+  for (int k = 0; k < count; ++k) {
+    args[k].wg0 = k * nwg;
+    args[k].nwg = nwg;
+  }
+  std::memcpy(c->bpinned, args.data(), (size_t)count * sizeof(IrlsArgs));
+  if (nwg > 1) {
+    int* map = reinterpret_cast<int*>((char*)c->bpinned + (size_t)count * sizeof(IrlsArgs));
+    for (int b = 0; b < count * nwg; ++b) map[b] = b / nwg;
+  }
+  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, solve_args_bytes(count, nwg), hipMemcpyHostToDevice,
+                         c->stream));
+  return FCT_OK;
+}
+
+static hipError_t launch_solve_alike(const IrlsArgs* args_dev, int count, bool f64, hipStream_t st, int nwg) {
+  if (nwg <= 1) return launch_irls_batched(args_dev, count, f64, st);
+  const int* map = reinterpret_cast<const int*>(args_dev + count);
+  return launch_irls_batched(args_dev, count, f64, st, map, count * nwg, true);
+}
+
 int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_t d, int64_t lda,
                      fct_dtype dt, double eps, const fct_params* prm_in, int32_t K, int32_t mode,
                      double* x, double* obj, int64_t* S, int32_t* status) {
@@ -1565,19 +1611,20 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
   if (perr) return FCT_ERR_BAD_ARG;
   // one sampling pass: R, lambda, sum lambda; then K draws, each with its
   // coreset, and the solver's arguments, outputs and work
+  const int nwg = alike_solve_wgs(c, K, cap);
   auto layout = [&](auto& cv) {
     cv.template take<double>((size_t)q * q);
     cv.template take<float>((size_t)n);
     cv.template take<double>(1);
     cv.template take<int64_t>((size_t)K);
-    cv.template take<char>((size_t)K * sizeof(IrlsArgs));
+    cv.template take<char>(solve_args_bytes(K, nwg));
     cv.template take<double>((size_t)K * 72);
     for (int k = 0; k < K; ++k) {
       cv.template take<char>((size_t)cap * d * es);
       cv.template take<char>((size_t)cap * es);
       cv.template take<double>((size_t)cap);
       cv.template take<int64_t>((size_t)cap);
-      cv.template take<double>(irls_batched_work_doubles(d));
+      cv.template take<double>(irls_batched_work_doubles(d, nwg));
       cv.template take<double>(72);
       cv.template take<int>(4);
     }
@@ -1592,14 +1639,14 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
   carve_select(mc, n);
   const size_t rest = std::max(ma.off, std::max(mb.off, mc.off)) + 1024;
   if ((st = ensure_scratch(c, fixed + rest + 256))) return st;
-  const size_t pin = std::max((size_t)K * sizeof(IrlsArgs), (size_t)K * 72 * sizeof(double));
+  const size_t pin = std::max(solve_args_bytes(K, nwg), (size_t)K * 72 * sizeof(double));
   if ((st = batch_ensure_aux(c, pin))) return st;
   Carve cv(c->scratch);
   double* R = cv.take<double>((size_t)q * q);
   float* lam = cv.take<float>((size_t)n);
   double* sl = cv.take<double>(1);
   int64_t* S_dev = cv.take<int64_t>((size_t)K);
-  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>((size_t)K * sizeof(IrlsArgs)));
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>(solve_args_bytes(K, nwg)));
   double* out_dev = cv.take<double>((size_t)K * 72);
   std::vector<IrlsArgs> args((size_t)K);
   std::vector<int64_t*> idx((size_t)K);
@@ -1609,7 +1656,7 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
     a.bt = cv.take<char>((size_t)cap * es);
     a.w = cv.take<double>((size_t)cap);
     idx[k] = cv.take<int64_t>((size_t)cap);
-    double* work = cv.take<double>(irls_batched_work_doubles(d));
+    double* work = cv.take<double>(irls_batched_work_doubles(d, nwg));
     double* outv = cv.take<double>(72);
     a.status = cv.take<int>(4);
     a.S_dev = S_dev + k;
@@ -1617,9 +1664,9 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
     a.ldat = cap;
     a.d = d;
     a.iters = iters;
-    a.row_target = 1 << 30;
+    a.row_target = solve_row_target(cap, nwg);
     a.part = work;
-    a.bar = irls_batched_bar(work, d);
+    a.bar = irls_batched_bar(work, d, nwg);
     a.x_out = outv;
     a.obj_out = outv + 64;
   }
@@ -1654,12 +1701,10 @@ int l1_regress_multi(fct_ctx* c, const void* A, const void* b, int64_t n, int32_
     HIP_TRY(launch_gather(A, b, lda, d, 1, n, idx[k], S_dev + k, cap, const_cast<void*>(args[k].At),
                           const_cast<void*>(args[k].bt), cap, dt == FCT_F64, c->stream));
   }
-  std::memcpy(c->bpinned, args.data(), (size_t)K * sizeof(IrlsArgs));
-  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)K * sizeof(IrlsArgs), hipMemcpyHostToDevice,
-                         c->stream));
+  if ((st = upload_solve_args(c, args, nwg, args_dev))) return st;
   HIP_TRY(hipStreamSynchronize(c->stream));  // the pinned block is reused for the outputs
   prof_begin(c, 2);
-  HIP_TRY(launch_irls_batched(args_dev, K, dt == FCT_F64, c->stream));
+  HIP_TRY(launch_solve_alike(args_dev, K, dt == FCT_F64, c->stream, nwg));
   prof_end(c, 2);
   hipLaunchKernelGGL(batch_collect_kernel, dim3(K), dim3(64), 0, c->stream, args_dev, K, out_dev);
   HIP_TRY(hipGetLastError());
@@ -1738,6 +1783,7 @@ int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t
   int perr = 0;
   const Pass1Plan plan = make_pass1_plan(c, n_pad, q, prm.s, prm.r1, es, prm.flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
+  const int nwg = alike_solve_wgs(c, k, cap);
   auto layout = [&](auto& cv) {
     cv.template take<double>((size_t)q * q);
     cv.template take<float>((size_t)n);
@@ -1747,10 +1793,10 @@ int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t
     cv.template take<char>((size_t)cap * k * es);
     cv.template take<double>((size_t)cap);
     cv.template take<int64_t>((size_t)cap);
-    cv.template take<char>((size_t)k * sizeof(IrlsArgs));
+    cv.template take<char>(solve_args_bytes(k, nwg));
     cv.template take<double>((size_t)k * 72);
     for (int j = 0; j < k; ++j) {
-      cv.template take<double>(irls_batched_work_doubles(d));
+      cv.template take<double>(irls_batched_work_doubles(d, nwg));
       cv.template take<double>(72);
       cv.template take<int>(4);
     }
@@ -1762,7 +1808,7 @@ int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t
   carve_probs(mb, c, q, prm.r2, n, dt == FCT_F64 ? kPass2F64 : kPass2F32);
   carve_select(mc, n);
   if ((st = ensure_scratch(c, m.off + std::max(ma.off, std::max(mb.off, mc.off)) + 1280))) return st;
-  const size_t pin = std::max((size_t)k * sizeof(IrlsArgs), (size_t)k * 72 * sizeof(double));
+  const size_t pin = std::max(solve_args_bytes(k, nwg), (size_t)k * 72 * sizeof(double));
   if ((st = batch_ensure_aux(c, pin))) return st;
   Carve cv(c->scratch);
   double* R = cv.take<double>((size_t)q * q);
@@ -1773,12 +1819,12 @@ int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t
   char* Bt = cv.take<char>((size_t)cap * k * es);
   double* w = cv.take<double>((size_t)cap);
   int64_t* idx = cv.take<int64_t>((size_t)cap);
-  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>((size_t)k * sizeof(IrlsArgs)));
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>(solve_args_bytes(k, nwg)));
   double* out_dev = cv.take<double>((size_t)k * 72);
   std::vector<IrlsArgs> args((size_t)k);
   for (int j = 0; j < k; ++j) {
     IrlsArgs& a = args[j];
-    double* work = cv.take<double>(irls_batched_work_doubles(d));
+    double* work = cv.take<double>(irls_batched_work_doubles(d, nwg));
     double* outv = cv.take<double>(72);
     a.status = cv.take<int>(4);
     a.At = At;
@@ -1789,9 +1835,9 @@ int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t
     a.ldat = cap;
     a.d = d;
     a.iters = iters;
-    a.row_target = 1 << 30;
+    a.row_target = solve_row_target(cap, nwg);
     a.part = work;
-    a.bar = irls_batched_bar(work, d);
+    a.bar = irls_batched_bar(work, d, nwg);
     a.x_out = outv;
     a.obj_out = outv + 64;
   }
@@ -1823,12 +1869,10 @@ int l1_regress_mrhs(fct_ctx* c, const void* A, const void* B, int64_t n, int32_t
   if (lambda_out)
     HIP_TRY(hipMemcpyAsync(lambda_out, lam, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
-  std::memcpy(c->bpinned, args.data(), (size_t)k * sizeof(IrlsArgs));
-  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)k * sizeof(IrlsArgs), hipMemcpyHostToDevice,
-                         c->stream));
+  if ((st = upload_solve_args(c, args, nwg, args_dev))) return st;
   HIP_TRY(hipStreamSynchronize(c->stream));
   prof_begin(c, 2);
-  HIP_TRY(launch_irls_batched(args_dev, k, dt == FCT_F64, c->stream));
+  HIP_TRY(launch_solve_alike(args_dev, k, dt == FCT_F64, c->stream, nwg));
   prof_end(c, 2);
   hipLaunchKernelGGL(batch_collect_kernel, dim3(k), dim3(64), 0, c->stream, args_dev, k, out_dev);
   HIP_TRY(hipGetLastError());
@@ -1876,6 +1920,7 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
   const Pass1Plan plan = make_pass1_plan(c, n_pad, q, prm.s, prm.r1, es, prm.flags, &perr);
   if (perr) return FCT_ERR_BAD_ARG;
   const int dj = d - 1;
+  const int nwg = alike_solve_wgs(c, d, cap);
   auto layout = [&](auto& cv) {
     cv.template take<double>((size_t)q * q);
     cv.template take<float>((size_t)n);
@@ -1886,10 +1931,10 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
     cv.template take<char>((size_t)cap * d * es);
     cv.template take<double>((size_t)cap);
     cv.template take<int64_t>((size_t)cap);
-    cv.template take<char>((size_t)d * sizeof(IrlsArgs));
+    cv.template take<char>(solve_args_bytes(d, nwg));
     cv.template take<double>((size_t)d * 72);
     for (int j = 0; j < d; ++j) {
-      cv.template take<double>(irls_batched_work_doubles(dj));
+      cv.template take<double>(irls_batched_work_doubles(dj, nwg));
       cv.template take<double>(72);
       cv.template take<int>(4);
     }
@@ -1901,7 +1946,7 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
   carve_probs(mb, c, q, prm.r2, n, dt == FCT_F64 ? kPass2F64 : kPass2F32);
   carve_select(mc, n);
   if ((st = ensure_scratch(c, m.off + std::max(ma.off, std::max(mb.off, mc.off)) + 1280))) return st;
-  const size_t pin = std::max((size_t)d * sizeof(IrlsArgs), (size_t)d * 72 * sizeof(double));
+  const size_t pin = std::max(solve_args_bytes(d, nwg), (size_t)d * 72 * sizeof(double));
   if ((st = batch_ensure_aux(c, pin))) return st;
   Carve cv(c->scratch);
   double* R = cv.take<double>((size_t)q * q);
@@ -1913,12 +1958,12 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
   char* bj = cv.take<char>((size_t)cap * d * es);
   double* w = cv.take<double>((size_t)cap);
   int64_t* idx = cv.take<int64_t>((size_t)cap);
-  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>((size_t)d * sizeof(IrlsArgs)));
+  IrlsArgs* args_dev = reinterpret_cast<IrlsArgs*>(cv.take<char>(solve_args_bytes(d, nwg)));
   double* out_dev = cv.take<double>((size_t)d * 72);
   std::vector<IrlsArgs> args((size_t)d);
   for (int j = 0; j < d; ++j) {
     IrlsArgs& a = args[j];
-    double* work = cv.take<double>(irls_batched_work_doubles(dj));
+    double* work = cv.take<double>(irls_batched_work_doubles(dj, nwg));
     double* outv = cv.take<double>(72);
     a.status = cv.take<int>(4);
     a.At = Aj + (size_t)j * cap * dj * es;
@@ -1929,9 +1974,9 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
     a.ldat = cap;
     a.d = dj;
     a.iters = iters;
-    a.row_target = 1 << 30;
+    a.row_target = solve_row_target(cap, nwg);
     a.part = work;
-    a.bar = irls_batched_bar(work, dj);
+    a.bar = irls_batched_bar(work, dj, nwg);
     a.x_out = outv;
     a.obj_out = outv + 64;
   }
@@ -1964,12 +2009,10 @@ int l1_subspace(fct_ctx* c, const void* A, int64_t n, int32_t d, int64_t lda, fc
   if (lambda_out)
     HIP_TRY(hipMemcpyAsync(lambda_out, lam, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice,
                            c->stream));
-  std::memcpy(c->bpinned, args.data(), (size_t)d * sizeof(IrlsArgs));
-  HIP_TRY(hipMemcpyAsync(args_dev, c->bpinned, (size_t)d * sizeof(IrlsArgs), hipMemcpyHostToDevice,
-                         c->stream));
+  if ((st = upload_solve_args(c, args, nwg, args_dev))) return st;
   HIP_TRY(hipStreamSynchronize(c->stream));
   prof_begin(c, 2);
-  HIP_TRY(launch_irls_batched(args_dev, d, dt == FCT_F64, c->stream));
+  HIP_TRY(launch_solve_alike(args_dev, d, dt == FCT_F64, c->stream, nwg));
   prof_end(c, 2);
   hipLaunchKernelGGL(batch_collect_kernel, dim3(d), dim3(64), 0, c->stream, args_dev, d, out_dev);
   HIP_TRY(hipGetLastError());
