@@ -1374,7 +1374,7 @@ int l1_regress_batched(fct_ctx* c, const fct_instance* inst, int32_t count, fct_
     for (int i = 0; i < count; ++i) nbig += cost[i] * 4.0 >= mx;
     const int resident = irls_max_resident_wgs(c->cus);
     const int per = nbig > 0 ? resident / nbig : 0;
-    if (nbig < count && per >= 2) {
+    if (per >= 2) {
       for (int i = 0; i < count; ++i) {
         if (cost[i] * 4.0 >= mx) {
           const int byrows = (int)std::max<int64_t>(1, items[i].cap / 256);
